@@ -1,0 +1,217 @@
+"""Throughput of the NU-FDS reconstruction on one MI355X.
+
+Default workload: the 16384^2, 120 deg full view (pitch lambda / (2 sin 60 deg), lambda = 0.5 um,
+1024 seeded points with z ~ U[10, 20] mm, reconstruction at z = 15 mm onto 16384^2 output pixels).
+A step is one whole reconstruction (FFT of the hologram, stretch-gather, inverse FFT, Fresnel
+transform, remap) of one hologram already resident in HBM.  ``value`` is output Mpixel/s of the
+complex64 path (float64 maps and phases); the complex128 path is reported beside it.
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LAM = 0.5e-6
+
+WORKLOADS = {
+    # name: (N, fov_deg, z, n_points, z_lo, z_hi, seed)
+    "uwa120_16k": (16384, 120.0, 15e-3, 1024, 10e-3, 20e-3, 1003),
+    "wa90_4k": (4096, 90.0, 7.5e-3, 4096, 5e-3, 10e-3, 1002),
+    "fov60_1k": (1024, 60.0, 3e-3, 64, 2e-3, 4e-3, 1001),
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uwa120_16k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
+    return ap.parse_args()
+
+
+def time_steps(plan, H, out, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.execute(H, out)
+    torch.cuda.synchronize()
+    plan.set_timing(steps)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        plan.execute(H, out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    launches = plan.timings()
+    plan.set_timing(0)
+    return ms, launches
+
+
+def kernel_table(launches, steps):
+    agg = {}
+    for name, ms, nbytes in launches:
+        a = agg.setdefault(name, {"ms": 0.0, "n": 0, "bytes": nbytes})
+        a["ms"] += ms
+        a["n"] += 1
+    table = {}
+    for name, a in agg.items():
+        avg = a["ms"] / a["n"]
+        table[name] = {"avg_ms": avg, "launches_per_step": a["n"] / steps, "bytes": a["bytes"],
+                       "gbs": a["bytes"] / (avg * 1e-3) / 1e9}
+    return table
+
+
+def cpu_baseline(torch, N):
+    """The float64 oracle on a bounded sample: the 120 deg geometry at 1024^2 (z scaled by 1/16 so
+    the aperture-to-distance ratio is that of the 16384^2 workload), 16 points.  The oracle's cost does
+    not depend on the hologram's content.  numpy runs it on one thread.  Returns the record and the
+    relative L2 error of both GPU paths on the same sample."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    n, fov = 1024, 120.0
+    scale = n / 16384
+    dp = synth.fov_pitch(LAM, fov)
+    z = 15e-3 * scale
+    pc = synth.draw_points(1003, 16, n, n, dp, LAM, 10e-3 * scale, 20e-3 * scale)
+    H = synth.point_hologram(pc, n, n, dp, LAM)
+    log("cpu baseline: oracle on the 1024^2 sample ...")
+    t0 = time.perf_counter()
+    ref = oracle.reconstruct(H, LAM, dp, z)
+    dt = time.perf_counter() - t0
+    rec = {"value": n * n / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+           "sample": (f"float64 oracle, full 1024^2 view of a 1024^2 120 deg hologram (16 points) at "
+                      f"z = {z * 1e3:.4f} mm (16384^2 geometry scaled by 1/16), one run of {dt:.1f} s on "
+                      f"{os.cpu_count()} host cores ({platform.processor() or platform.machine()}); "
+                      f"numpy uses one thread")}
+    errs = {}
+    for prec in ("c64", "c128"):
+        plan = N.Plan(LAM, dp, n, n, z, precision=prec)
+        host = H.astype(np.complex64) if prec == "c64" else H
+        out = plan(torch.from_numpy(host).cuda())
+        torch.cuda.synchronize()
+        r = oracle.reconstruct(host.astype(np.complex128), LAM, dp, z) if prec == "c64" else ref
+        errs[prec] = oracle.rel_l2(out.cpu().numpy().astype(np.complex128), r)
+        plan.close()
+    return rec, errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(this path runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2410_13474_amd import nufds as N
+
+    N.load()
+    torch.cuda.set_device(0)
+    n, fov, z, npts, zlo, zhi, seed = WORKLOADS[args.workload]
+    dp = synth.fov_pitch(LAM, fov)
+    log(f"workload {args.workload}: N={n} fov={fov} z={z} points={npts}")
+    pc = synth.draw_points(seed, npts, n, n, dp, LAM, zlo, zhi)
+    H128 = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    N.synth_hologram(pc.as_array(), n, n, dp, LAM, H128)
+    H64 = H128.to(torch.complex64)
+    torch.cuda.synchronize()
+    log("hologram generated on the GPU (float64 sum, rounded to complex64)")
+
+    results = {}
+    outs = {}
+    for prec in (("c64",) if args.no_fp64 else ("c64", "c128")):
+        t0 = time.perf_counter()
+        plan = N.Plan(LAM, dp, n, n, z, precision=prec)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        H = H64 if prec == "c64" else H128
+        out = torch.empty((plan.info["sy"], plan.info["sx"]), dtype=plan.dtype, device="cuda")
+        ms, launches = time_steps(plan, H, out, args.steps, args.warmup, torch)
+        kt = kernel_table(launches, args.steps)
+        mpix = plan.info["sx"] * plan.info["sy"] / (ms * 1e-3) / 1e6
+        log(f"{prec}: {ms:.3f} ms/step, {mpix:.1f} Mpix/s, plan {t_plan:.2f} s, M={plan.info['mx']}")
+        for name, k in sorted(kt.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches_per_step"]):
+            log(f"   {name:16s} {k['avg_ms']:8.3f} ms x{k['launches_per_step']:.0f}  {k['gbs']:7.0f} GB/s")
+        alg_bytes = sum(k["bytes"] * k["launches_per_step"] for k in kt.values())
+        results[prec] = {"ms_per_step": ms, "mpix_s": mpix, "plan_s": t_plan, "kernels": kt,
+                         "alg_bytes_per_step": alg_bytes, "frac_hbm_end_to_end": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "info": {k: plan.info[k] for k in ("mx", "my", "kcx", "kcy", "workspace_bytes", "map_bytes")}}
+        outs[prec] = out
+        del plan
+    rel_fp32_fp64 = None
+    if "c128" in outs:
+        a = outs["c64"].to(torch.complex128)
+        b = outs["c128"]
+        rel_fp32_fp64 = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        log(f"rel L2 complex64 vs complex128 GPU paths: {rel_fp32_fp64:.3e}")
+    del outs
+
+    main_r = results["c64"]
+    kt = main_r["kernels"]
+    dom = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches_per_step"])
+    d = kt[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        cpu, errs = cpu_baseline(torch, N)
+        log(f"cpu baseline {cpu['value']:.4f} Mpix/s; sample rel L2 vs oracle: {errs}")
+
+    line = {
+        "metric": "NU-FDS Mpix/s 16K 120° (FP32 vs FP64 @ rel-L2); p50/p99 partial-view ms",
+        "value": main_r["mpix_s"],
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "hologram": f"{n}x{n}", "fov_deg": fov, "z_m": z,
+                   "points": npts, "seed": seed, "output": f"{n}x{n} full view"},
+        "fp64": ({"value": results["c128"]["mpix_s"], "ms_per_step": results["c128"]["ms_per_step"],
+                  "dtype": "c128"} if "c128" in results else None),
+        "rel_l2": {"fp32_vs_fp64_gpu": rel_fp32_fp64, "sample_vs_oracle": errs or None},
+        "roofline": roofline,
+        "end_to_end_hbm_frac": main_r["frac_hbm_end_to_end"],
+        "kernels": {p: {k: {"avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),
+                            "per_step": v["launches_per_step"]} for k, v in r["kernels"].items()}
+                    for p, r in results.items()},
+        "partial_view_latency_ms": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

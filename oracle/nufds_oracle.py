@@ -545,7 +545,8 @@ def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
         px, py = KX + nx // 2, KY + ny // 2
         u = KX * wavelength / (nx * pitch)
         v = KY * wavelength / (ny * pitch)
-        valid = (np.abs(u) <= s) & (np.abs(v) <= s)
+        # |u| <= s is |k_g| <= N/2 in index units; tested exactly there
+        valid = (np.abs(KX) <= nx // 2) & (np.abs(KY) <= ny // 2)
     else:
         up = KX * wavelength / (nx * pitch)
         vp = KY * wavelength / (ny * pitch)

@@ -1,0 +1,869 @@
+// C ABI of libnufds: plan geometry, plan lifecycle and the execute sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fft.h"
+#include "kernels.h"
+#include "nufds.h"
+#include "special.h"
+
+namespace nufds {
+
+#define NUFDS_TRY(x)                        \
+    do {                                    \
+        nufds_status_t st_ = (x);           \
+        if (st_ != NUFDS_OK) return st_;    \
+    } while (0)
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+nufds_status_t fail(nufds_status_t st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+nufds_status_t hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? NUFDS_ERR_OUT_OF_MEMORY : NUFDS_ERR_HIP;
+}
+
+// ------------------------------------------------------------------ geometry
+
+static bool smooth5(int n) {
+    if (n <= 0) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static int smooth5_even_at_least(long n) {
+    if (n < 2) n = 2;
+    for (long m = n;; ++m)
+        if (m % 2 == 0 && smooth5((int)m)) return (int)m;
+}
+
+// x' of Eqs. 17-18 for the true point (x, y) at distance z: A(x) R^-1/2.
+static double xprime(double x, double y, double z) {
+    const double r = std::sqrt(x * x + y * y + z * z);
+    return output_map_factor(x, z) / std::sqrt(r);
+}
+
+// Extremes of x' over the window [xlo, xhi] x [ylo, yhi]: x' grows with x and its magnitude
+// falls with |y|, so both sit on the vertical edges, at the y nearest 0 when the edge lies on the
+// same side as the extreme and at the farthest y otherwise.
+static void xprime_extremes(double xlo, double xhi, double ylo, double yhi, double z, bool remap, double* lo,
+                            double* hi) {
+    if (!remap) {
+        *lo = xlo;
+        *hi = xhi;
+        return;
+    }
+    const double ynear = std::min(std::max(0.0, ylo), yhi);
+    const double yfar = std::fabs(ylo) > std::fabs(yhi) ? ylo : yhi;
+    *hi = xprime(xhi, xhi >= 0.0 ? ynear : yfar, z);
+    *lo = xprime(xlo, xlo <= 0.0 ? ynear : yfar, z);
+}
+
+nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny, double z, const nufds_view_t* view,
+                                uint32_t flags, const nufds_options_t* opt, nufds_plan_info_t* out) {
+    if (!out) return fail(NUFDS_ERR_INVALID_ARG, "out is NULL");
+    if (!(wavelength > 0.0) || !(pitch > 0.0) || !(z > 0.0) || !std::isfinite(wavelength) || !std::isfinite(pitch) ||
+        !std::isfinite(z))
+        return fail(NUFDS_ERR_INVALID_ARG, "wavelength, pitch and z must be positive and finite");
+    const double s = wavelength / (2.0 * pitch);
+    if (!(s < 1.0)) return fail(NUFDS_ERR_INVALID_ARG, "wavelength / (2 pitch) must be < 1");
+    if (nx <= 0 || ny <= 0 || (nx & 1) || (ny & 1)) return fail(NUFDS_ERR_INVALID_ARG, "hologram sizes must be even and positive");
+    if (flags & ~7u) return fail(NUFDS_ERR_INVALID_ARG, "unknown flag bits");
+    std::memset(out, 0, sizeof(*out));
+    const double B = 2.0 * z * std::tan(std::asin(s));
+    const double dfx = wavelength * z / (nx * pitch);
+    const double dfy = wavelength * z / (ny * pitch);
+    double cx = 0, cy = 0, dox, doy;
+    int sx, sy;
+    if (!view) {
+        sx = nx;
+        sy = ny;
+        dox = B / nx;
+        doy = B / ny;
+    } else {
+        cx = view->center_x;
+        cy = view->center_y;
+        sx = view->nx;
+        sy = view->ny;
+        dox = view->pitch_x > 0.0 ? view->pitch_x : dfx;
+        doy = view->pitch_y > 0.0 ? view->pitch_y : dfy;
+        if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(dox) || !std::isfinite(doy))
+            return fail(NUFDS_ERR_INVALID_ARG, "view values must be finite");
+    }
+    if (sx <= 0 || sy <= 0) return fail(NUFDS_ERR_INVALID_ARG, "view size must be positive");
+    const double xlo = cx - 0.5 * sx * dox, xhi = cx + 0.5 * sx * dox;
+    const double ylo = cy - 0.5 * sy * doy, yhi = cy + 0.5 * sy * doy;
+    const double tol = 1e-9 * B;
+    if (xlo < -0.5 * B - tol || xhi > 0.5 * B + tol || ylo < -0.5 * B - tol || yhi > 0.5 * B + tol)
+        return fail(NUFDS_ERR_INVALID_ARG, "view window leaves the image area [-B/2, B/2]^2 of Eq. 1");
+    const bool remap = !(flags & NUFDS_FLAG_NO_REMAP);
+    double xl, xh, yl, yh;
+    xprime_extremes(xlo, xhi, ylo, yhi, z, remap, &xl, &xh);
+    xprime_extremes(ylo, yhi, xlo, xhi, z, remap, &yl, &yh);
+    double padx = 0.5 * nx * pitch, pady = 0.5 * ny * pitch;
+    int forced_x = 0, forced_y = 0;
+    if (opt) {
+        if (opt->pad >= 0.0) padx = pady = opt->pad;
+        forced_x = opt->frt_size_x;
+        forced_y = opt->frt_size_y;
+        if (forced_x < 0 || forced_y < 0 || (forced_x & 1) || (forced_y & 1))
+            return fail(NUFDS_ERR_INVALID_ARG, "forced FrT sizes must be even and non-negative");
+    }
+    auto axis = [](double lo, double hi, double df, double pad, int forced, int* kc, int* m) {
+        lo -= pad;
+        hi += pad;
+        const double k = std::floor(0.5 * (lo + hi) / df + 0.5);
+        const double half = std::max(hi - k * df, k * df - lo) / df;
+        *kc = (int)k;
+        if (forced) {
+            *m = forced;
+        } else {
+            const double need = 2.0 * std::ceil(half - 1e-9);
+            *m = need > 1e9 ? -1 : smooth5_even_at_least((long)need);
+        }
+    };
+    int kcx, kcy, mx, my;
+    axis(xl, xh, dfx, padx, forced_x, &kcx, &mx);
+    axis(yl, yh, dfy, pady, forced_y, &kcy, &my);
+    out->nx = nx;
+    out->ny = ny;
+    out->sx = sx;
+    out->sy = sy;
+    out->mx = mx;
+    out->my = my;
+    out->kcx = kcx;
+    out->kcy = kcy;
+    out->dfx = dfx;
+    out->dfy = dfy;
+    out->dox = dox;
+    out->doy = doy;
+    out->cx = cx;
+    out->cy = cy;
+    out->image_size = B;
+    out->xlo = xl;
+    out->xhi = xh;
+    out->ylo = yl;
+    out->yhi = yh;
+    out->padx = padx;
+    out->pady = pady;
+    out->flags = flags;
+    if (mx <= 0 || my <= 0) return fail(NUFDS_ERR_UNSUPPORTED, "FrT size out of range");
+    return NUFDS_OK;
+}
+
+// ------------------------------------------------------------------ plan
+
+constexpr int kMaxLen = 65536;
+
+// Largest T(1) of the map over the band square |u|, |v| <= s of the unit disk: at u = s and the
+// largest admissible |v| (T_1 grows with both |u| and |v|).
+static double stretch_extent(double s) {
+    const double v = std::min(s, std::sqrt((1.0 - s) * (1.0 + s)));
+    const double av = std::sqrt((1.0 - v) * (1.0 + v));
+    const double sig = std::min(1.0, s / av);
+    const double c = std::sqrt(std::max(0.0, (1.0 - sig) * (1.0 + sig)));
+    return std::sqrt(av) * integral_i(sig, c);
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace nufds
+
+using namespace nufds;
+
+struct nufds_plan {
+    nufds_plan_info_t info{};
+    double wavelength = 0, pitch = 0, z = 0;
+    uint32_t flags = 0;
+    int prec = 0;
+    int device = 0;
+    size_t esize = 8;
+    DevBuf spec, work1, work2, table, chirp_x, chirp_y, ax, by;
+    int kxt = -1, kyt = -1;
+    std::map<int, void*> twiddles;
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_run = false;
+    void* result = nullptr;  // buffer holding F after the last execute
+    int tile_cap = 0;        // LDS tile capacity override captured at creation (0: none)
+    // per-launch timing
+    int timing_cap = 0;                        // executes to record (0: timing off)
+    int timed_execs = 0;                       // executes recorded so far
+    bool recording = false;                    // the current execute is being recorded
+    std::vector<hipEvent_t> ev;                // pairs (start, end) per recorded launch
+    std::vector<nufds_kernel_time_t> launches; // names and bytes of the recorded launches
+    int nlaunch = 0;
+};
+
+namespace nufds {
+
+static nufds_status_t dev_alloc(DevBuf& b, size_t bytes) {
+    b.bytes = bytes;
+    if (bytes == 0) return NUFDS_OK;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(NUFDS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return NUFDS_OK;
+}
+
+static void dev_free(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static void plan_free(nufds_plan* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    dev_free(p->spec);
+    dev_free(p->work1);
+    dev_free(p->work2);
+    dev_free(p->table);
+    dev_free(p->chirp_x);
+    dev_free(p->chirp_y);
+    dev_free(p->ax);
+    dev_free(p->by);
+    for (auto& kv : p->twiddles) (void)hipFree(kv.second);
+    p->twiddles.clear();
+    if (p->done) (void)hipEventDestroy(p->done);
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    delete p;
+}
+
+template <typename R>
+static nufds_status_t upload_complex(DevBuf& b, const std::vector<double>& re, const std::vector<double>& im) {
+    std::vector<cpx<R>> h(re.size());
+    for (size_t i = 0; i < re.size(); ++i) h[i] = mk(R(re[i]), R(im[i]));
+    nufds_status_t st = dev_alloc(b, h.size() * sizeof(cpx<R>));
+    if (st != NUFDS_OK) return st;
+    NUFDS_HIP_TRY(hipMemcpy(b.p, h.data(), b.bytes, hipMemcpyHostToDevice));
+    return NUFDS_OK;
+}
+
+// exp(-2 pi i m / L), m = 0 .. L-1, in float64 then rounded.
+template <typename R>
+static nufds_status_t twiddle_table(nufds_plan* p, int L, const cpx<R>** out) {
+    auto it = p->twiddles.find(L);
+    if (it != p->twiddles.end()) {
+        *out = static_cast<const cpx<R>*>(it->second);
+        return NUFDS_OK;
+    }
+    std::vector<cpx<R>> h(L);
+    for (int m = 0; m < L; ++m) {
+        // angle reduced to the first octant-friendly form: use (m / L) in [0, 1)
+        const double a = -2.0 * M_PI * (double)m / (double)L;
+        h[m] = mk(R(std::cos(a)), R(std::sin(a)));
+    }
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, L * sizeof(cpx<R>));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddles)");
+    e = hipMemcpy(d, h.data(), L * sizeof(cpx<R>), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "hipMemcpy(twiddles)");
+    }
+    p->twiddles[L] = d;
+    *out = static_cast<const cpx<R>*>(d);
+    return NUFDS_OK;
+}
+
+// The chirp exp(+i k xi^2 / 2z) of Eq. 2 at xi = (n - M/2) N D / M, phase in float64 reduced mod 2 pi.
+static void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::vector<double>& re,
+                         std::vector<double>& im) {
+    re.resize(M);
+    im.resize(M);
+    const double cycles_per_m2 = 1.0 / (2.0 * wavelength * z);  // k xi^2 / 2z = 2 pi xi^2 / (2 lambda z)
+    for (int n = 0; n < M; ++n) {
+        const double xi = (double)(n - M / 2) * (N * pitch / M);
+        double cyc = xi * xi * cycles_per_m2;
+        cyc -= std::floor(cyc);
+        const double ph = 2.0 * M_PI * cyc;
+        re[n] = std::cos(ph);
+        im[n] = std::sin(ph);
+    }
+}
+
+// ---------------------------------------------------------- pass construction
+
+struct Limits {
+    int tile_elems;  // LDS tile capacity, elements
+    int col_w;       // columns per tile (128-byte runs)
+    int max_elems;   // register budget per thread and stage
+};
+
+// NUFDS_MAX_TILE_ELEMS lowers the LDS tile capacity (tests use it to drive the four-step passes
+// at small sizes); a plan reads it once, when it is created.
+static int tile_override() {
+    const char* e = std::getenv("NUFDS_MAX_TILE_ELEMS");
+    return e ? std::atoi(e) : 0;
+}
+
+static Limits limits_for(size_t esize, int cap) {
+    Limits l;
+    l.tile_elems = (int)((160 * 1024) / esize);
+    if (cap > 0) l.tile_elems = std::min(l.tile_elems, cap);
+    l.col_w = esize == 8 ? 16 : 8;
+    l.max_elems = esize == 8 ? 32 : 16;
+    return l;
+}
+
+static int ilog2(int w) {
+    int l = 0;
+    while ((1 << l) < w) ++l;
+    return l;
+}
+
+static bool finish_desc(PassDesc& d, const Limits& lim) {
+    if (!factor_radices(d.L, &d.nst, d.rad)) return false;
+    d.logW = ilog2(d.W);
+    if ((1 << d.logW) != d.W) return false;
+    if ((int64_t)d.L * d.W > lim.tile_elems) return false;
+    d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
+    return d.nthreads > 0;
+}
+
+// Split L = L1 L2 so that both passes' tiles (L1 x W and L2 x W) fit, as balanced as possible.
+static bool four_step_split(int L, int W, const Limits& lim, int* L1, int* L2) {
+    int best = -1, best_span = 0;
+    for (int a = 2; a < L; ++a) {
+        if (L % a) continue;
+        const int b = L / a;
+        if ((int64_t)a * W > lim.tile_elems || (int64_t)b * W > lim.tile_elems) continue;
+        const int span = std::max(a, b);
+        if (best < 0 || span < best_span) {
+            best = a;
+            best_span = span;
+        }
+    }
+    if (best < 0) return false;
+    *L1 = best;
+    *L2 = L / best;
+    return true;
+}
+
+// The passes of one axis transform of a [rows][cols] array (axis 0: along rows = x; axis 1: along
+// columns = y), for a single forward/inverse transform (chain = 0) or the IDFT . vec . DFT chain
+// (chain = 1).  Fills 'passes'; the caller binds buffers.
+struct AxisPlan {
+    bool single = true;
+    std::vector<PassDesc> passes;  // single: 1 pass; four-step: 2 (plain) or 4 (chain)
+};
+
+static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int chain, const Limits& lim,
+                       AxisPlan* ap) {
+    ap->passes.clear();
+    PassDesc d{};
+    d.sign = sign;
+    d.in_pitch = d.out_pitch = pitch;
+    if (axis == 0) {
+        d.rows = other;
+        d.cols = L;
+        if (L <= lim.tile_elems) {
+            d.kind = K_ROW1;
+            d.L = L;
+            int w = 1;
+            while (w < 16 && (int64_t)L * w * 2 <= 4096 && (int64_t)L * w * 2 <= lim.tile_elems) w *= 2;
+            d.W = w;
+            d.chain = chain;
+            d.tiles_a = (other + w - 1) / w;
+            d.tiles_b = 1;
+            if (!finish_desc(d, lim)) return false;
+            ap->single = true;
+            ap->passes.push_back(d);
+            return true;
+        }
+    } else {
+        d.rows = L;
+        d.cols = other;
+        if ((int64_t)L * lim.col_w <= lim.tile_elems) {
+            d.kind = K_COL1;
+            d.L = L;
+            d.W = lim.col_w;
+            d.chain = chain;
+            d.tiles_a = 1;
+            d.tiles_b = (other + d.W - 1) / d.W;
+            if (!finish_desc(d, lim)) return false;
+            ap->single = true;
+            ap->passes.push_back(d);
+            return true;
+        }
+    }
+    // four-step
+    int L1, L2;
+    const int W = lim.col_w;
+    if (!four_step_split(L, W, lim, &L1, &L2)) return false;
+    ap->single = false;
+    const int nt = chain ? 2 : 1;
+    for (int t = 0; t < nt; ++t) {
+        const int sg = t == 0 ? sign : -sign;
+        PassDesc a = d, b = d;
+        a.L1 = b.L1 = L1;
+        a.L2 = b.L2 = L2;
+        a.Lf = b.Lf = L;
+        a.sign = b.sign = sg;
+        a.chain = b.chain = 0;
+        a.W = b.W = W;
+        a.L = L1;
+        b.L = L2;
+        if (axis == 0) {
+            a.kind = K_ROWA;
+            a.tiles_a = other;
+            a.tiles_b = (L2 + W - 1) / W;
+            b.kind = K_ROWB;
+            b.tiles_a = other;
+            b.tiles_b = (L1 + W - 1) / W;
+        } else {
+            a.kind = K_COLA;
+            a.tiles_a = L2;
+            a.tiles_b = (other + W - 1) / W;
+            b.kind = K_COLB;
+            b.tiles_a = L1;
+            b.tiles_b = (other + W - 1) / W;
+        }
+        if (!finish_desc(a, lim) || !finish_desc(b, lim)) return false;
+        ap->passes.push_back(a);
+        ap->passes.push_back(b);
+    }
+    return true;
+}
+
+// ---------------------------------------------------------- execute
+
+// Timing bracket: when the plan times its executes, record an event pair around the launch.
+static nufds_status_t timing_begin(nufds_plan* p, const char* name, uint64_t bytes, hipStream_t s) {
+    if (!p->recording) return NUFDS_OK;
+    const size_t i = (size_t)p->nlaunch;
+    while (p->ev.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        NUFDS_HIP_TRY(hipEventCreate(&e));
+        p->ev.push_back(e);
+    }
+    if (p->launches.size() < i + 1) p->launches.resize(i + 1);
+    nufds_kernel_time_t& k = p->launches[i];
+    std::memset(&k, 0, sizeof(k));
+    std::strncpy(k.name, name, sizeof(k.name) - 1);
+    k.bytes = bytes;
+    NUFDS_HIP_TRY(hipEventRecord(p->ev[2 * i], s));
+    return NUFDS_OK;
+}
+
+static nufds_status_t timing_end(nufds_plan* p, hipStream_t s) {
+    if (!p->recording) return NUFDS_OK;
+    NUFDS_HIP_TRY(hipEventRecord(p->ev[2 * (size_t)p->nlaunch + 1], s));
+    ++p->nlaunch;
+    return NUFDS_OK;
+}
+
+// Algorithmic bytes of an FFT pass over a [rows][cols] array: every element read once and written once.
+static uint64_t pass_bytes(const PassDesc& d, size_t esize) { return 2ull * d.rows * d.cols * esize; }
+
+template <typename R>
+static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& d, const void* in, void* out,
+                               int load_conj, int load_sign, int store_sign, R store_scale, const cpx<R>* store_vec,
+                               const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+    const cpx<R>* tw;
+    nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
+    if (st != NUFDS_OK) return st;
+    const cpx<R>* twf = nullptr;
+    if (d.kind == K_ROWA || d.kind == K_COLA) {
+        st = twiddle_table<R>(p, d.Lf, &twf);
+        if (st != NUFDS_OK) return st;
+    }
+    LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1)};
+    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_vec, store_sign, store_scale};
+    NUFDS_TRY(timing_begin(p, name, pass_bytes(d, sizeof(cpx<R>)), s));
+    NUFDS_HIP_TRY((launch_pass<R, LoadPlain<R>>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
+    return timing_end(p, s);
+}
+
+template <typename R>
+static nufds_status_t run_gather_pass(nufds_plan* p, const char* name, const PassDesc& d, void* out, int store_sign,
+                                      R store_scale,
+                                      const cpx<R>* store_vec, const cpx<R>* chainvec, R chainscale,
+                                      hipStream_t s) {
+    const cpx<R>* tw;
+    nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
+    if (st != NUFDS_OK) return st;
+    const cpx<R>* twf = nullptr;
+    if (d.kind == K_ROWA) {
+        st = twiddle_table<R>(p, d.Lf, &twf);
+        if (st != NUFDS_OK) return st;
+    }
+    LoadGather<R> ld;
+    ld.spec = static_cast<const cpx<R>*>(p->spec.p);
+    ld.table = static_cast<const double*>(p->table.p);
+    ld.nx = p->info.nx;
+    ld.ny = p->info.ny;
+    ld.kxt = p->kxt;
+    ld.kyt = p->kyt;
+    ld.mx = p->info.mx;
+    ld.my = p->info.my;
+    ld.kcx = p->info.kcx;
+    ld.kcy = p->info.kcy;
+    ld.nostretch = (p->flags & NUFDS_FLAG_NO_STRETCH) ? 1 : 0;
+    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_vec, store_sign, store_scale};
+    // algorithmic bytes: the quadrant table entries, the spectrum region the band pulls from
+    // (at most the whole spectrum), and the sub-band written once
+    const uint64_t es = sizeof(cpx<R>);
+    const uint64_t mm = (uint64_t)p->info.mx * p->info.my, nn = (uint64_t)p->info.nx * p->info.ny;
+    const uint64_t bytes = p->table.bytes + std::min(mm, nn) * es + mm * es;
+    NUFDS_TRY(timing_begin(p, name, bytes, s));
+    NUFDS_HIP_TRY((launch_pass<R, LoadGather<R>>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
+    return timing_end(p, s);
+}
+
+
+template <typename R>
+static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out, hipStream_t s) {
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap);
+    const nufds_plan_info_t& g = p->info;
+    const int nx = g.nx, ny = g.ny, mx = g.mx, my = g.my;
+    void* spec = p->spec.p;
+    void* w1 = p->work1.p;
+    void* w2 = p->work2.p;
+    const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
+    AxisPlan ap;
+
+    // step 2a: centred forward DFT of the hologram, Ĥ[k] = (-1)^(k + N/2) DFT[(-1)^n H] per axis
+    if (!build_axis(0, nx, ny, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram row length");
+    const R sgx = ((nx / 2) & 1) ? R(-1) : R(1);
+    if (ap.single) {
+        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, nullptr, R(1), s));
+    } else {
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, nullptr, R(1), s));
+    }
+    if (!build_axis(1, ny, nx, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram column length");
+    const R sgy = ((ny / 2) & 1) ? R(-1) : R(1);
+    if (ap.single) {
+        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, nullptr, R(1), s));
+    } else {
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, nullptr, R(1), s));
+    }
+
+    // steps 2b-3 along x: stretch-gather, centred IDFT, chirp / M_x, centred DFT (signs cancel to
+    // (-1)^k' on input and (-1)^m on output)
+    const cpx<R>* cxv = static_cast<const cpx<R>*>(p->chirp_x.p);
+    const cpx<R>* cyv = static_cast<const cpx<R>*>(p->chirp_y.p);
+    if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
+    void* res;
+    if (ap.single) {
+        NUFDS_TRY(run_gather_pass<R>(p, "xop_gather", ap.passes[0], w1, 1, R(1), nullptr, cxv, R(1) / R(mx), s));
+        res = w1;
+    } else {
+        NUFDS_TRY(run_gather_pass<R>(p, "xop_gather_a", ap.passes[0], w1, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_idft_b", ap.passes[1], w1, w2, 0, 0, 0, R(1) / R(mx), cxv, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_dft_a", ap.passes[2], w2, w1, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_dft_b", ap.passes[3], w1, w2, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        res = w2;
+    }
+    // and along y
+    if (!build_axis(1, my, mx, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
+    if (ap.single) {
+        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), nullptr, cyv, R(1) / R(my), s));
+    } else {
+        void* oth = (res == w1) ? w2 : w1;
+        NUFDS_TRY(run_pass<R>(p, "yop_idft_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_idft_b", ap.passes[1], oth, res, 0, 0, 0, R(1) / R(my), cyv, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_dft_a", ap.passes[2], res, oth, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_dft_b", ap.passes[3], oth, res, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+    }
+    p->result = res;
+
+    // step 5: output gather
+    OutputArgs<R> oa;
+    oa.F = static_cast<const cpx<R>*>(res);
+    oa.out = static_cast<cpx<R>*>(d_out);
+    oa.ax = static_cast<const double*>(p->ax.p);
+    oa.by = static_cast<const double*>(p->by.p);
+    oa.sx = g.sx;
+    oa.sy = g.sy;
+    oa.mx = mx;
+    oa.my = my;
+    oa.kcx = g.kcx;
+    oa.kcy = g.kcy;
+    oa.cx = g.cx;
+    oa.cy = g.cy;
+    oa.dox = g.dox;
+    oa.doy = g.doy;
+    oa.dfx = g.dfx;
+    oa.dfy = g.dfy;
+    oa.z = p->z;
+    oa.kz2 = (2.0 * M_PI / p->wavelength) / (2.0 * p->z);
+    oa.remap = (p->flags & NUFDS_FLAG_NO_REMAP) ? 0 : 1;
+    oa.conj_out = conj_in;
+    // algorithmic bytes: the FrT samples under the window's distorted image (plus the 4-tap
+    // support), read once, and the output written once
+    const double fxs = std::min((double)mx, (g.xhi - g.xlo) / g.dfx + 4.0);
+    const double fys = std::min((double)my, (g.yhi - g.ylo) / g.dfy + 4.0);
+    const uint64_t obytes = (uint64_t)(fxs * fys) * sizeof(cpx<R>) + (uint64_t)g.sx * g.sy * sizeof(cpx<R>);
+    NUFDS_TRY(timing_begin(p, "output_gather", obytes, s));
+    NUFDS_HIP_TRY(launch_output_gather<R>(oa, s));
+    return timing_end(p, s);
+}
+
+template <typename R>
+static nufds_status_t prepare_impl(nufds_plan* p) {
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap);
+    const nufds_plan_info_t& g = p->info;
+    // every transform must have a pass plan; create the twiddle tables its passes read, so that
+    // execute only enqueues kernels
+    const int axes[4][5] = {{0, g.nx, g.ny, g.nx, 0}, {1, g.ny, g.nx, g.nx, 0}, {0, g.mx, g.my, g.mx, 1},
+                            {1, g.my, g.mx, g.mx, 1}};
+    for (const auto& a : axes) {
+        AxisPlan ap;
+        if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap))
+            return fail(NUFDS_ERR_UNSUPPORTED, "no FFT pass plan for a transform of length " + std::to_string(a[1]));
+        for (const PassDesc& d : ap.passes) {
+            const cpx<R>* t;
+            NUFDS_TRY(twiddle_table<R>(p, d.L, &t));
+            if (d.kind == K_ROWA || d.kind == K_COLA) NUFDS_TRY(twiddle_table<R>(p, d.Lf, &t));
+        }
+    }
+    // chirp vectors
+    std::vector<double> re, im;
+    chirp_vector(g.mx, g.nx, p->pitch, p->wavelength, p->z, re, im);
+    NUFDS_TRY(upload_complex<R>(p->chirp_x, re, im));
+    chirp_vector(g.my, g.ny, p->pitch, p->wavelength, p->z, re, im);
+    NUFDS_TRY(upload_complex<R>(p->chirp_y, re, im));
+    return NUFDS_OK;
+}
+
+static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, double pitch, int32_t nx, int32_t ny,
+                                       double z, const nufds_view_t* view, nufds_precision_t precision,
+                                       uint32_t flags, const nufds_options_t* opt) {
+    if (!out) return fail(NUFDS_ERR_INVALID_ARG, "plan is NULL");
+    *out = nullptr;
+    if (precision != NUFDS_C64 && precision != NUFDS_C128) return fail(NUFDS_ERR_INVALID_ARG, "unknown precision");
+    nufds_plan_info_t g;
+    NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z, view, flags, opt, &g));
+    if (g.mx > kMaxLen || g.my > kMaxLen || nx > kMaxLen || ny > kMaxLen || !smooth5(nx) || !smooth5(ny))
+        return fail(NUFDS_ERR_UNSUPPORTED, "sizes must be 5-smooth and at most 65536");
+    nufds_plan* p = new (std::nothrow) nufds_plan();
+    if (!p) return fail(NUFDS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->info = g;
+    p->info.precision = precision;
+    p->wavelength = wavelength;
+    p->pitch = pitch;
+    p->z = z;
+    p->flags = flags;
+    p->prec = precision;
+    p->esize = precision == NUFDS_C64 ? 8 : 16;
+    p->tile_cap = tile_override();
+    auto bail = [&](nufds_status_t st) {
+        std::string msg = nufds_last_error();
+        plan_free(p);
+        set_error(msg);
+        return st;
+    };
+    hipError_t he = hipGetDevice(&p->device);
+    if (he != hipSuccess) return bail(hip_fail(he, "hipGetDevice"));
+    const size_t nn = (size_t)nx * ny, mm = (size_t)g.mx * g.my;
+    const size_t big = std::max(nn, mm);
+    nufds_status_t st;
+    if ((st = dev_alloc(p->spec, nn * p->esize)) != NUFDS_OK) return bail(st);
+    if ((st = dev_alloc(p->work1, big * p->esize)) != NUFDS_OK) return bail(st);
+    if ((st = dev_alloc(p->work2, big * p->esize)) != NUFDS_OK) return bail(st);
+    // stretch-map table: quadrant |k_g| <= min(band extent, stretch extent) per axis
+    const double s = wavelength / (2.0 * pitch);
+    if (!(flags & NUFDS_FLAG_NO_STRETCH)) {
+        const double ext = stretch_extent(s);
+        const int kmx = (int)std::floor(ext * nx * pitch / wavelength) + 2;
+        const int kmy = (int)std::floor(ext * ny * pitch / wavelength) + 2;
+        const int bx = std::max(std::abs(g.kcx - g.mx / 2), std::abs(g.kcx + g.mx / 2 - 1));
+        const int by = std::max(std::abs(g.kcy - g.my / 2), std::abs(g.kcy + g.my / 2 - 1));
+        p->kxt = std::min(bx, kmx);
+        p->kyt = std::min(by, kmy);
+        const size_t entries = (size_t)(p->kxt + 1) * (p->kyt + 1);
+        if ((st = dev_alloc(p->table, entries * 2 * sizeof(double))) != NUFDS_OK) return bail(st);
+        he = launch_map_table(static_cast<double*>(p->table.p), p->kxt, p->kyt, wavelength, nx * pitch, ny * pitch, s,
+                              nullptr);
+        if (he != hipSuccess) return bail(hip_fail(he, "map table launch"));
+    }
+    // output-map factors A(x_j), B(y_i) (Eqs. 17-18), float64 on the host
+    if (!(flags & NUFDS_FLAG_NO_REMAP)) {
+        std::vector<double> ax(g.sx), by(g.sy);
+        for (int j = 0; j < g.sx; ++j) ax[j] = output_map_factor(g.cx + (double)(j - g.sx / 2) * g.dox, z);
+        for (int i = 0; i < g.sy; ++i) by[i] = output_map_factor(g.cy + (double)(i - g.sy / 2) * g.doy, z);
+        if ((st = dev_alloc(p->ax, g.sx * sizeof(double))) != NUFDS_OK) return bail(st);
+        if ((st = dev_alloc(p->by, g.sy * sizeof(double))) != NUFDS_OK) return bail(st);
+        he = hipMemcpy(p->ax.p, ax.data(), p->ax.bytes, hipMemcpyHostToDevice);
+        if (he == hipSuccess) he = hipMemcpy(p->by.p, by.data(), p->by.bytes, hipMemcpyHostToDevice);
+        if (he != hipSuccess) return bail(hip_fail(he, "hipMemcpy(output map)"));
+    }
+    st = precision == NUFDS_C64 ? prepare_impl<float>(p) : prepare_impl<double>(p);
+    if (st != NUFDS_OK) return bail(st);
+    he = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (he != hipSuccess) return bail(hip_fail(he, "hipEventCreate"));
+    he = hipDeviceSynchronize();
+    if (he != hipSuccess) return bail(hip_fail(he, "plan build"));
+    size_t total = p->spec.bytes + p->work1.bytes + p->work2.bytes + p->table.bytes + p->chirp_x.bytes +
+                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes;
+    p->info.map_bytes = p->table.bytes;
+    p->info.workspace_bytes = total;
+    *out = p;
+    return NUFDS_OK;
+}
+
+}  // namespace nufds
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+nufds_status_t nufds_plan_geometry(double wavelength, double pitch, int32_t nx, int32_t ny, double z,
+                                   const nufds_view_t* view, uint32_t flags, const nufds_options_t* opt,
+                                   nufds_plan_info_t* out) {
+    nufds_status_t st = compute_geometry(wavelength, pitch, nx, ny, z, view, flags, opt, out);
+    if (st == NUFDS_OK) set_error("");
+    return st;
+}
+
+nufds_status_t nufds_plan_create(nufds_plan_t* plan, double wavelength, double pitch, int32_t nx, int32_t ny,
+                                 double z, const nufds_view_t* view, nufds_precision_t precision, uint32_t flags) {
+    return plan_create_impl(plan, wavelength, pitch, nx, ny, z, view, precision, flags, nullptr);
+}
+
+nufds_status_t nufds_plan_create_ex(nufds_plan_t* plan, double wavelength, double pitch, int32_t nx, int32_t ny,
+                                    double z, const nufds_view_t* view, nufds_precision_t precision, uint32_t flags,
+                                    const nufds_options_t* opt) {
+    return plan_create_impl(plan, wavelength, pitch, nx, ny, z, view, precision, flags, opt);
+}
+
+nufds_status_t nufds_plan_info(nufds_plan_t plan, nufds_plan_info_t* out) {
+    if (!plan || !out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    *out = plan->info;
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_out, void* stream) {
+    if (!plan || !d_hologram || !d_out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    if (d_hologram == d_out) return fail(NUFDS_ERR_INVALID_ARG, "output aliases the hologram");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->has_run && s != plan->last_stream) {
+        hipError_t q = hipEventQuery(plan->done);
+        if (q == hipErrorNotReady) return fail(NUFDS_ERR_BUSY, "previous execute still running on another stream");
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    plan->recording = plan->timed_execs < plan->timing_cap;
+    nufds_status_t st = plan->prec == NUFDS_C64 ? execute_impl<float>(plan, d_hologram, d_out, s)
+                                                : execute_impl<double>(plan, d_hologram, d_out, s);
+    if (plan->recording) ++plan->timed_execs;
+    plan->recording = false;
+    if (st != NUFDS_OK) return st;
+    NUFDS_HIP_TRY(hipEventRecord(plan->done, s));
+    plan->last_stream = s;
+    plan->has_run = true;
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_debug_copy(nufds_plan_t plan, int32_t which, void* d_dst, uint64_t* bytes, void* stream) {
+    if (!plan || !bytes) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    const void* src = nullptr;
+    uint64_t n = 0;
+    switch (which) {
+        case 1: src = plan->spec.p; n = (uint64_t)plan->info.nx * plan->info.ny * plan->esize; break;
+        case 2: src = plan->result; n = (uint64_t)plan->info.mx * plan->info.my * plan->esize; break;
+        case 3: src = plan->table.p; n = plan->table.bytes; break;
+        default: return fail(NUFDS_ERR_INVALID_ARG, "unknown buffer");
+    }
+    *bytes = n;
+    if (!d_dst) return NUFDS_OK;
+    if (!src) return fail(NUFDS_ERR_INVALID_ARG, "buffer not available (no execute yet, or no table)");
+    NUFDS_HIP_TRY(hipMemcpyAsync(d_dst, src, n, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_set_timing(nufds_plan_t plan, int32_t n_executes) {
+    if (!plan || n_executes < 0) return fail(NUFDS_ERR_INVALID_ARG, "NULL plan or negative count");
+    NUFDS_HIP_TRY(hipDeviceSynchronize());
+    plan->timing_cap = n_executes;
+    plan->timed_execs = 0;
+    plan->nlaunch = 0;
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_get_timings(nufds_plan_t plan, nufds_kernel_time_t* out, int32_t max_entries,
+                                 int32_t* n_entries) {
+    if (!plan || !n_entries) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    if (plan->timing_cap == 0) return fail(NUFDS_ERR_INVALID_ARG, "timing is not enabled");
+    const int n = plan->nlaunch;
+    *n_entries = n;
+    if (!out) return NUFDS_OK;
+    if (n > 0) NUFDS_HIP_TRY(hipEventSynchronize(plan->ev[2 * (size_t)n - 1]));
+    for (int i = 0; i < n && i < max_entries; ++i) {
+        float ms = 0.0f;
+        NUFDS_HIP_TRY(hipEventElapsedTime(&ms, plan->ev[2 * (size_t)i], plan->ev[2 * (size_t)i + 1]));
+        out[i] = plan->launches[i];
+        out[i].ms = ms;
+    }
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_destroy(nufds_plan_t plan) {
+    plan_free(plan);
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_synth_hologram(const double* h_points, int32_t n_points, int32_t nx, int32_t ny, double pitch,
+                                    double wavelength, nufds_precision_t precision, void* d_out, void* stream) {
+    if (!h_points || n_points <= 0 || nx <= 0 || ny <= 0 || !d_out || !(pitch > 0) || !(wavelength > 0))
+        return fail(NUFDS_ERR_INVALID_ARG, "invalid synth arguments");
+    if (precision != NUFDS_C64 && precision != NUFDS_C128) return fail(NUFDS_ERR_INVALID_ARG, "unknown precision");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* d_pts = nullptr;
+    const size_t bytes = (size_t)n_points * 5 * sizeof(double);
+    hipError_t e = hipMallocAsync(&d_pts, bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(points)");
+    e = hipMemcpyAsync(d_pts, h_points, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host array may go away after return
+    if (e == hipSuccess) {
+        const double k = 2.0 * M_PI / wavelength;
+        e = precision == NUFDS_C64
+                ? launch_synth<float>(static_cast<double*>(d_pts), n_points, nx, ny, pitch, k, static_cast<cpx<float>*>(d_out), s)
+                : launch_synth<double>(static_cast<double*>(d_pts), n_points, nx, ny, pitch, k, static_cast<cpx<double>*>(d_out), s);
+    }
+    hipError_t e2 = hipFreeAsync(d_pts, s);
+    if (e != hipSuccess) return hip_fail(e, "synth");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync(points)");
+    return NUFDS_OK;
+}
+
+const char* nufds_status_string(nufds_status_t status) {
+    switch (status) {
+        case NUFDS_OK: return "ok";
+        case NUFDS_ERR_INVALID_ARG: return "invalid argument";
+        case NUFDS_ERR_UNSUPPORTED: return "unsupported";
+        case NUFDS_ERR_OUT_OF_MEMORY: return "out of memory";
+        case NUFDS_ERR_HIP: return "HIP error";
+        case NUFDS_ERR_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char* nufds_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

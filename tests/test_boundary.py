@@ -1,0 +1,146 @@
+"""The C-ABI boundary on the CPU: symbols, host geometry against the oracle, error paths.
+
+No compute call reaches the GPU here; nufds_plan_geometry is host-only.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_2410_13474_amd import nufds as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "nufds.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nufds_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.load()
+    names = _header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N._SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings():
+    lib = N.load()
+    for st, text in [(0, b"ok"), (1, b"invalid argument"), (2, b"unsupported"), (3, b"out of memory"),
+                     (4, b"HIP error"), (5, b"busy")]:
+        assert lib.nufds_status_string(st) == text
+
+
+CASES = [
+    # n, fov, z, view (None = full), flags
+    (1024, 60.0, 3e-3, None, 0),
+    (4096, 90.0, 7.5e-3, None, 0),
+    (16384, 120.0, 15e-3, None, 0),
+    (8192, 120.0, 5e-3, None, 0),
+    (512, 120.0, 1e-3, dict(center_x=2e-4, center_y=-3e-4, pitch_x=0.0, pitch_y=0.0, nx=200, ny=136), 0),
+    (512, 90.0, 1e-3, dict(center_x=-1e-4, center_y=5e-5, pitch_x=1.3e-6, pitch_y=0.9e-6, nx=64, ny=96), 0),
+    (256, 60.0, 1e-3, dict(center_x=1e-4, center_y=1e-4, pitch_x=0.0, pitch_y=0.0, nx=50, ny=30), O.NO_REMAP),
+]
+
+
+@pytest.mark.parametrize("n,fov,z,view,flags", CASES)
+def test_geometry_matches_oracle(n, fov, z, view, flags):
+    lam = 0.5e-6
+    dp = synth.fov_pitch(lam, fov)
+    g = N.plan_geometry(lam, dp, n, n, z, view=view, flags=flags)
+    b = O.plan_band(n, n, lam, dp, z, view=view, flags=flags)
+    assert (g["mx"], g["my"], g["kcx"], g["kcy"], g["sx"], g["sy"]) == (b.mx, b.my, b.kcx, b.kcy, b.sx, b.sy)
+    for k_lib, k_or in [("dfx", "dfx"), ("dox", "dox"), ("doy", "doy"), ("xlo", "xlo"), ("xhi", "xhi"),
+                        ("ylo", "ylo"), ("yhi", "yhi")]:
+        assert abs(g[k_lib] - getattr(b, k_or)) <= 1e-12 * max(1e-9, abs(getattr(b, k_or)))
+    assert abs(g["image_size"] - O.image_size(lam, dp, z)) <= 1e-15
+
+
+def test_geometry_random_views_match_oracle():
+    rng = np.random.default_rng(4)
+    lam = 0.5e-6
+    for _ in range(60):
+        fov = rng.choice([60.0, 90.0, 100.0, 120.0])
+        n = int(rng.choice([256, 512, 1024, 2048, 8192]))
+        nyy = int(rng.choice([n, n // 2]))
+        dp = synth.fov_pitch(lam, fov)
+        z = rng.uniform(0.5, 20) * 1e-3
+        B = O.image_size(lam, dp, z)
+        sx, sy = int(rng.integers(1, 700)), int(rng.integers(1, 700))
+        do = rng.uniform(0.2, 3.0) * lam * z / (n * dp)
+        half_x, half_y = 0.5 * sx * do, 0.5 * sy * do
+        if half_x > 0.5 * B or half_y > 0.5 * B:
+            continue
+        cx = rng.uniform(-0.5 * B + half_x, 0.5 * B - half_x)
+        cy = rng.uniform(-0.5 * B + half_y, 0.5 * B - half_y)
+        view = dict(center_x=cx, center_y=cy, pitch_x=do, pitch_y=do, nx=sx, ny=sy)
+        flags = int(rng.choice([0, O.NO_REMAP]))
+        g = N.plan_geometry(lam, dp, n, nyy, z, view=view, flags=flags)
+        b = O.plan_band(n, nyy, lam, dp, z, view=view, flags=flags)
+        assert (g["mx"], g["my"], g["kcx"], g["kcy"]) == (b.mx, b.my, b.kcx, b.kcy)
+
+
+def test_geometry_pad_and_forced_size():
+    lam, dp, z = 0.5e-6, 0.5e-6, 2e-3
+    g = N.plan_geometry(lam, dp, 256, 256, z, pad=0.0)
+    b = O.plan_band(256, 256, lam, dp, z, pad=0.0)
+    assert (g["mx"], g["kcx"]) == (b.mx, b.kcx)
+    g = N.plan_geometry(lam, dp, 256, 256, z, frt_size=(400, 360))
+    assert (g["mx"], g["my"]) == (400, 360)
+
+
+@pytest.mark.parametrize("args", [
+    (0.0, 0.5e-6, 256, 256, 1e-3),        # wavelength
+    (0.5e-6, 0.25e-6, 256, 256, 1e-3),    # lambda / 2 pitch >= 1
+    (0.5e-6, 0.5e-6, 255, 256, 1e-3),     # odd size
+    (0.5e-6, 0.5e-6, 256, 0, 1e-3),       # empty
+    (0.5e-6, 0.5e-6, 256, 256, -1e-3),    # z
+    (0.5e-6, 0.5e-6, 256, 256, float("nan")),
+])
+def test_geometry_rejects_invalid_arguments(args):
+    with pytest.raises(N.NufdsError) as e:
+        N.plan_geometry(*args)
+    assert e.value.status == N.ERR_INVALID_ARG
+
+
+def test_geometry_rejects_window_outside_image():
+    lam, dp, z = 0.5e-6, 0.5e-6, 3e-3
+    B = O.image_size(lam, dp, z)
+    with pytest.raises(N.NufdsError) as e:
+        N.plan_geometry(lam, dp, 256, 256, z, view=dict(center_x=0.45 * B, center_y=0, pitch_x=0, pitch_y=0,
+                                                         nx=256, ny=16))
+    assert e.value.status == N.ERR_INVALID_ARG
+    with pytest.raises(N.NufdsError) as e:
+        N.plan_geometry(lam, dp, 256, 256, z, view=dict(center_x=0, center_y=0, pitch_x=0, pitch_y=0,
+                                                         nx=0, ny=16))
+    assert e.value.status == N.ERR_INVALID_ARG
+    with pytest.raises(N.NufdsError):
+        N.plan_geometry(lam, dp, 256, 256, z, flags=64)
+
+
+def test_null_arguments_are_rejected():
+    lib = N.load()
+    assert lib.nufds_plan_geometry(0.5e-6, 0.5e-6, 64, 64, 1e-3, None, 0, None, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_plan_info(None, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_execute(None, None, None, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_destroy(None) == N.OK
+    h = ctypes.c_void_p()
+    assert lib.nufds_plan_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, 1e-3, None, 7, 0) == N.ERR_INVALID_ARG
+    assert h.value is None
+    assert lib.nufds_synth_hologram(None, 0, 64, 64, 0.5e-6, 0.5e-6, 0, None, None) == N.ERR_INVALID_ARG
+    assert b"invalid" in lib.nufds_last_error()
+
+
+def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        N.load()
