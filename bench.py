@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", default="uwa120_16k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (a reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -131,6 +133,14 @@ def main():
 
     N.load()
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies done")
+        del src, dst
     n, fov, z, npts, zlo, zhi, seed = WORKLOADS[args.workload]
     dp = synth.fov_pitch(LAM, fov)
     log(f"workload {args.workload}: N={n} fov={fov} z={z} points={npts}")
