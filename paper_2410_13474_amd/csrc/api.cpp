@@ -322,7 +322,8 @@ static int tile_override() {
 
 static Limits limits_for(size_t esize, int cap) {
     Limits l;
-    l.tile_elems = (int)((160 * 1024) / esize);
+    // logical elements whose padded LDS footprint (one pad per 32) fits in 160 KB
+    l.tile_elems = (int)(((160 * 1024) / esize - 1) * 32 / 33);
     if (cap > 0) l.tile_elems = std::min(l.tile_elems, cap);
     l.col_w = esize == 8 ? 16 : 8;
     l.max_elems = esize == 8 ? 32 : 16;
@@ -339,7 +340,7 @@ static bool finish_desc(PassDesc& d, const Limits& lim) {
     if (!factor_radices(d.L, &d.nst, d.rad)) return false;
     d.logW = ilog2(d.W);
     if ((1 << d.logW) != d.W) return false;
-    if ((int64_t)d.L * d.W > lim.tile_elems) return false;
+    if ((int64_t)d.L * d.W > lim.tile_elems) return false;  // padded LDS footprint within 160 KB
     d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
     return d.nthreads > 0;
 }
@@ -371,12 +372,16 @@ struct AxisPlan {
     std::vector<PassDesc> passes;  // single: 1 pass; four-step: 2 (plain) or 4 (chain)
 };
 
+// gather_w > 0: the single-pass row transform carries the stretch-gather; its tiles then go to the
+// XCDs in contiguous row ranges so that neighbouring rows (neighbouring spectrum rows) share an L2.
+// In the four-step case the gather runs as a kernel of its own and every pass is plain.
 static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int chain, const Limits& lim,
-                       AxisPlan* ap) {
+                       AxisPlan* ap, int gather_w = 0) {
     ap->passes.clear();
     PassDesc d{};
     d.sign = sign;
     d.in_pitch = d.out_pitch = pitch;
+    d.xcd_rows = 0;
     if (axis == 0) {
         d.rows = other;
         d.cols = L;
@@ -389,6 +394,7 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
             d.chain = chain;
             d.tiles_a = (other + w - 1) / w;
             d.tiles_b = 1;
+            d.xcd_rows = gather_w > 0 ? 1 : 0;
             if (!finish_desc(d, lim)) return false;
             ap->single = true;
             ap->passes.push_back(d);
@@ -410,41 +416,59 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
             return true;
         }
     }
-    // four-step
+    // four-step: A (over n1) then B (over n2); a chain fuses the first B and the second A
     int L1, L2;
     const int W = lim.col_w;
     if (!four_step_split(L, W, lim, &L1, &L2)) return false;
     ap->single = false;
-    const int nt = chain ? 2 : 1;
-    for (int t = 0; t < nt; ++t) {
-        const int sg = t == 0 ? sign : -sign;
-        PassDesc a = d, b = d;
-        a.L1 = b.L1 = L1;
-        a.L2 = b.L2 = L2;
-        a.Lf = b.Lf = L;
-        a.sign = b.sign = sg;
-        a.chain = b.chain = 0;
-        a.W = b.W = W;
-        a.L = L1;
-        b.L = L2;
+    PassDesc a = d, b = d;
+    a.L1 = b.L1 = L1;
+    a.L2 = b.L2 = L2;
+    a.Lf = b.Lf = L;
+    a.chain = b.chain = 0;
+    a.W = b.W = W;
+    a.L = L1;
+    b.L = L2;
+    if (axis == 0) {
+        a.kind = K_ROWA;
+        a.tiles_a = other;
+        a.tiles_b = (L2 + a.W - 1) / a.W;
+        b.kind = chain ? K_ROWBA : K_ROWB;
+        b.tiles_a = other;
+        b.tiles_b = (L1 + W - 1) / W;
+    } else {
+        a.kind = K_COLA;
+        a.tiles_a = L2;
+        a.tiles_b = (other + W - 1) / W;
+        b.kind = chain ? K_COLBA : K_COLB;
+        b.tiles_a = L1;
+        b.tiles_b = (other + W - 1) / W;
+    }
+    b.chain = chain;
+    if (!finish_desc(a, lim) || !finish_desc(b, lim)) return false;
+    ap->passes.push_back(a);
+    ap->passes.push_back(b);
+    if (chain) {
+        // the second transform's B pass, with the split taken as L = L2 L1
+        PassDesc c = d;
+        c.L1 = L2;
+        c.L2 = L1;
+        c.Lf = L;
+        c.L = L1;
+        c.W = W;
+        c.chain = 0;
+        c.sign = -sign;
         if (axis == 0) {
-            a.kind = K_ROWA;
-            a.tiles_a = other;
-            a.tiles_b = (L2 + W - 1) / W;
-            b.kind = K_ROWB;
-            b.tiles_a = other;
-            b.tiles_b = (L1 + W - 1) / W;
+            c.kind = K_ROWB;
+            c.tiles_a = other;
+            c.tiles_b = (L2 + W - 1) / W;
         } else {
-            a.kind = K_COLA;
-            a.tiles_a = L2;
-            a.tiles_b = (other + W - 1) / W;
-            b.kind = K_COLB;
-            b.tiles_a = L1;
-            b.tiles_b = (other + W - 1) / W;
+            c.kind = K_COLB;
+            c.tiles_a = L2;
+            c.tiles_b = (other + W - 1) / W;
         }
-        if (!finish_desc(a, lim) || !finish_desc(b, lim)) return false;
-        ap->passes.push_back(a);
-        ap->passes.push_back(b);
+        if (!finish_desc(c, lim)) return false;
+        ap->passes.push_back(c);
     }
     return true;
 }
@@ -487,7 +511,7 @@ static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& 
     nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
     if (st != NUFDS_OK) return st;
     const cpx<R>* twf = nullptr;
-    if (d.kind == K_ROWA || d.kind == K_COLA) {
+    if (d.kind == K_ROWA || d.kind == K_COLA || d.kind == K_ROWBA || d.kind == K_COLBA) {
         st = twiddle_table<R>(p, d.Lf, &twf);
         if (st != NUFDS_OK) return st;
     }
@@ -535,6 +559,47 @@ static nufds_status_t run_gather_pass(nufds_plan* p, const char* name, const Pas
 }
 
 
+// |k| range of band samples g0 .. g1 (inclusive) along one axis.
+static void abs_range(int g0, int g1, int* lo, int* hi) {
+    if (g0 <= 0 && g1 >= 0) {
+        *lo = 0;
+        *hi = std::max(-g0, g1);
+    } else {
+        *lo = std::min(std::abs(g0), std::abs(g1));
+        *hi = std::max(std::abs(g0), std::abs(g1));
+    }
+}
+
+template <typename R>
+static nufds_status_t run_stretch_gather(nufds_plan* p, void* out, hipStream_t s) {
+    const nufds_plan_info_t& g = p->info;
+    GatherArgs<R> a;
+    a.spec = static_cast<const cpx<R>*>(p->spec.p);
+    a.out = static_cast<cpx<R>*>(out);
+    a.table = static_cast<const double*>(p->table.p);
+    a.kxt = p->kxt;
+    a.kyt = p->kyt;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.mx = g.mx;
+    a.my = g.my;
+    a.gx0 = g.kcx - g.mx / 2;
+    a.gy0 = g.kcy - g.my / 2;
+    int lo, hi;
+    abs_range(a.gx0, a.gx0 + g.mx - 1, &lo, &hi);
+    a.ax0 = lo;
+    a.nax = hi - lo + 1;
+    abs_range(a.gy0, a.gy0 + g.my - 1, &lo, &hi);
+    a.ay0 = lo;
+    a.nay = hi - lo + 1;
+    a.nostretch = (p->flags & NUFDS_FLAG_NO_STRETCH) ? 1 : 0;
+    const uint64_t es = sizeof(cpx<R>);
+    const uint64_t mm = (uint64_t)g.mx * g.my, nn = (uint64_t)g.nx * g.ny;
+    NUFDS_TRY(timing_begin(p, "stretch_gather", p->table.bytes + std::min(mm, nn) * es + mm * es, s));
+    NUFDS_HIP_TRY(launch_stretch_gather<R>(a, s));
+    return timing_end(p, s);
+}
+
 template <typename R>
 static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap);
@@ -568,17 +633,18 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
     // (-1)^k' on input and (-1)^m on output)
     const cpx<R>* cxv = static_cast<const cpx<R>*>(p->chirp_x.p);
     const cpx<R>* cyv = static_cast<const cpx<R>*>(p->chirp_y.p);
-    if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
+    if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap, 64)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
     void* res;
     if (ap.single) {
         NUFDS_TRY(run_gather_pass<R>(p, "xop_gather", ap.passes[0], w1, 1, R(1), nullptr, cxv, R(1) / R(mx), s));
         res = w1;
     } else {
-        NUFDS_TRY(run_gather_pass<R>(p, "xop_gather_a", ap.passes[0], w1, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_idft_b", ap.passes[1], w1, w2, 0, 0, 0, R(1) / R(mx), cxv, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_dft_a", ap.passes[2], w2, w1, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_dft_b", ap.passes[3], w1, w2, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
-        res = w2;
+        // the four-step A tile is strided along the row: gather in a kernel of its own first
+        NUFDS_TRY(run_stretch_gather<R>(p, w2, s));
+        NUFDS_TRY(run_pass<R>(p, "xop_a", ap.passes[0], w2, w1, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_ba", ap.passes[1], w1, w2, 0, 0, 0, R(1), nullptr, cxv, R(1) / R(mx), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_b", ap.passes[2], w2, w1, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        res = w1;
     }
     // and along y
     if (!build_axis(1, my, mx, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
@@ -586,10 +652,10 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
         NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), nullptr, cyv, R(1) / R(my), s));
     } else {
         void* oth = (res == w1) ? w2 : w1;
-        NUFDS_TRY(run_pass<R>(p, "yop_idft_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_idft_b", ap.passes[1], oth, res, 0, 0, 0, R(1) / R(my), cyv, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_dft_a", ap.passes[2], res, oth, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_dft_b", ap.passes[3], oth, res, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), nullptr, cyv, R(1) / R(my), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        res = oth;
     }
     p->result = res;
 
@@ -609,8 +675,10 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
     oa.cy = g.cy;
     oa.dox = g.dox;
     oa.doy = g.doy;
-    oa.dfx = g.dfx;
-    oa.dfy = g.dfy;
+    oa.inv_dfx = 1.0 / g.dfx;
+    oa.inv_dfy = 1.0 / g.dfy;
+    oa.qx0 = (double)(mx / 2) - (double)g.kcx;
+    oa.qy0 = (double)(my / 2) - (double)g.kcy;
     oa.z = p->z;
     oa.kz2 = (2.0 * M_PI / p->wavelength) / (2.0 * p->z);
     oa.remap = (p->flags & NUFDS_FLAG_NO_REMAP) ? 0 : 1;
@@ -635,12 +703,13 @@ static nufds_status_t prepare_impl(nufds_plan* p) {
                             {1, g.my, g.mx, g.mx, 1}};
     for (const auto& a : axes) {
         AxisPlan ap;
-        if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap))
+        if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap, (a[4] && a[0] == 0) ? 64 : 0))
             return fail(NUFDS_ERR_UNSUPPORTED, "no FFT pass plan for a transform of length " + std::to_string(a[1]));
         for (const PassDesc& d : ap.passes) {
             const cpx<R>* t;
             NUFDS_TRY(twiddle_table<R>(p, d.L, &t));
-            if (d.kind == K_ROWA || d.kind == K_COLA) NUFDS_TRY(twiddle_table<R>(p, d.Lf, &t));
+            if (d.kind == K_ROWA || d.kind == K_COLA || d.kind == K_ROWBA || d.kind == K_COLBA)
+                NUFDS_TRY(twiddle_table<R>(p, d.Lf, &t));
         }
     }
     // chirp vectors

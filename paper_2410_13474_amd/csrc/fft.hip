@@ -136,6 +136,15 @@ __device__ __forceinline__ int fdiv(int j, int n, float inv) {
     return q;
 }
 
+// Powers w^1 .. w^(RAD-1) by a balanced product tree (w^t = w^(t/2) w^(t - t/2)): one table load
+// per butterfly, and every power is at most ~log2(RAD) rounded products away from the table value.
+template <typename R, int RAD>
+__device__ __forceinline__ void twiddle_powers(cpx<R> w, cpx<R>* wp) {
+    wp[1] = w;
+#pragma unroll
+    for (int t = 2; t < RAD; ++t) wp[t] = wp[t / 2] * wp[t - t / 2];
+}
+
 // One Stockham stage of radix RAD over the LDS tile (Govindaraju et al., SC 2008 formulation):
 // butterfly j reads x[j + t L/RAD], twiddles by w_(Ns RAD)^(t k), k = j mod Ns, and writes
 // (j / Ns) Ns RAD + k + t Ns.  All reads happen before the barrier, all writes after.
@@ -153,43 +162,57 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, int L, int lw, int Ns, co
     const int tstride = L / (Ns * RAD);
     const float inv = 1.0f / (float)Ns;
     cpx<R> v[NB][RAD];
+    cpx<R> cw[NB];
+    // reads: LDS inputs and the butterfly's twiddle, all issued before the barrier and without
+    // branches (butterflies past B read butterfly 0 and are not written back)
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        int b = tid_s + i * T;
-        if (b < B) {
-            int w = b & (W - 1), j = b >> lw;
+        const int b0 = tid_s + i * T;
+        const int b = b0 < B ? b0 : 0;
+        const int w = b & (W - 1), j = b >> lw;
+        const int q = fdiv(j, Ns, inv);
+        const int k = j - q * Ns;
+        cw[i] = tw[k * tstride];
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) v[i][t] = lds[((j + t * LR) << lw) + w];
-        }
+        for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_pad(((j + t * LR) << lw) + w)];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        int b = tid_s + i * T;
+        const int b = tid_s + i * T;
         if (b < B) {
-            int w = b & (W - 1), j = b >> lw;
-            int q = fdiv(j, Ns, inv);
-            int k = j - q * Ns;
-            if (k != 0) {
-                int step = k * tstride;
+            const int w = b & (W - 1), j = b >> lw;
+            const int q = fdiv(j, Ns, inv);
+            const int k = j - q * Ns;
+            cpx<R> c = cw[i];
+            if (sign > 0) c.y = -c.y;
+            if (sizeof(R) == 4) {
+                cpx<R> wp[RAD];
+                twiddle_powers<R, RAD>(c, wp);
+#pragma unroll
+                for (int t = 1; t < RAD; ++t) v[i][t] = v[i][t] * wp[t];
+            } else {
+                // float64: a running product (<= RAD - 2 roundings, ~1e-15) keeps registers free
+                cpx<R> p = c;
 #pragma unroll
                 for (int t = 1; t < RAD; ++t) {
-                    cpx<R> c = tw[t * step];
-                    if (sign > 0) c.y = -c.y;
-                    v[i][t] = v[i][t] * c;
+                    v[i][t] = v[i][t] * p;
+                    if (t + 1 < RAD) p = p * c;
                 }
             }
             SmallDft<R, RAD>::run(v[i], sign);
-            int base = q * Ns * RAD + k;
+            const int base = q * Ns * RAD + k;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) lds[((base + t * Ns) << lw) + w] = v[i][SmallDft<R, RAD>::perm(t)];
+            for (int t = 0; t < RAD; ++t)
+                lds[lds_pad(((base + t * Ns) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)];
         }
     }
     __syncthreads();
 }
 
 template <typename R, int MAXE>
-__device__ __forceinline__ void fft_tile(cpx<R>* lds, const PassDesc& d, const cpx<R>* __restrict__ tw, int sign, int tid, int T) {
+__device__ __forceinline__ void fft_tile(cpx<R>* lds, const PassDesc& d, const cpx<R>* __restrict__ tw, int sign,
+                                         int tid, int T) {
     int Ns = 1;
     for (int s = 0; s < d.nst; ++s) {
         const int r = d.rad[s];
@@ -206,11 +229,12 @@ __device__ __forceinline__ void fft_tile(cpx<R>* lds, const PassDesc& d, const c
 }
 
 // Affine description of one tile: element (n, w) lives at base + n sn + w sw; its index along the
-// transformed axis is n an + w aw + a0 (input) or k bn + w bw + b0 (output); the transverse index
-// is t0 + w t1; the four-step twiddle exponent is (m0 + w m1) k.
+// transformed axis is n an + w aw + a0 (input) or k bn + w bw + b0 (output); the chain multiply of a
+// fused pass reads the vector at n cn + w cw + c0; the transverse index is t0 + w t1; the four-step
+// twiddle exponent of the store is (m0 + w m1) k.
 struct TileMap {
     int64_t ib, isn, isw, ob, osn, osw;
-    int an, aw, a0, bn, bw, b0, t0, t1, m0, m1;
+    int an, aw, a0, bn, bw, b0, cn, cw, c0, t0, t1, m0, m1;
     int wvalid;
     bool in_nfast, out_nfast, twiddle;
 };
@@ -220,6 +244,7 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
     const int W = d.W;
     m.twiddle = false;
     m.m0 = m.m1 = 0;
+    m.cn = 1; m.cw = 0; m.c0 = 0;
     switch (d.kind) {
         case K_ROW1: {
             int r0 = a * W;
@@ -258,6 +283,18 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
             m.in_nfast = true; m.out_nfast = false;
             break;
         }
+        case K_ROWBA: {
+            // input as ROWB (k1 = k10 + w, n over k2); output position q1 L1 + k1 with twiddle w^(k1 q1)
+            int row = a, k10 = b * W;
+            m.wvalid = min(W, d.L1 - k10);
+            m.ib = row * d.in_pitch + (int64_t)k10 * d.L2; m.isn = 1; m.isw = d.L2;
+            m.ob = row * d.out_pitch + k10; m.osn = d.L1; m.osw = 1;
+            m.an = 0; m.aw = 0; m.a0 = 0; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = row; m.t1 = 0;
+            m.cn = d.L1; m.cw = 1; m.c0 = k10;
+            m.twiddle = true; m.m0 = k10; m.m1 = 1;
+            m.in_nfast = true; m.out_nfast = false;
+            break;
+        }
         case K_COLA: {
             int n2 = a, c0 = b * W;
             m.wvalid = min(W, d.cols - c0);
@@ -268,12 +305,23 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
             m.in_nfast = m.out_nfast = false;
             break;
         }
-        default: {  // K_COLB
+        case K_COLB: {
             int k1 = a, c0 = b * W;
             m.wvalid = min(W, d.cols - c0);
             m.ib = (int64_t)k1 * d.L2 * d.in_pitch + c0; m.isn = d.in_pitch; m.isw = 1;
             m.ob = k1 * d.out_pitch + c0; m.osn = (int64_t)d.L1 * d.out_pitch; m.osw = 1;
             m.an = 0; m.aw = 0; m.a0 = 0; m.bn = d.L1; m.bw = 0; m.b0 = k1; m.t0 = c0; m.t1 = 1;
+            m.in_nfast = m.out_nfast = false;
+            break;
+        }
+        default: {  // K_COLBA: input as COLB, output row q1 L1 + k1 with twiddle w^(k1 q1)
+            int k1 = a, c0 = b * W;
+            m.wvalid = min(W, d.cols - c0);
+            m.ib = (int64_t)k1 * d.L2 * d.in_pitch + c0; m.isn = d.in_pitch; m.isw = 1;
+            m.ob = k1 * d.out_pitch + c0; m.osn = (int64_t)d.L1 * d.out_pitch; m.osw = 1;
+            m.an = 0; m.aw = 0; m.a0 = 0; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = c0; m.t1 = 1;
+            m.cn = d.L1; m.cw = 0; m.c0 = k1;
+            m.twiddle = true; m.m0 = k1; m.m1 = 0;
             m.in_nfast = m.out_nfast = false;
             break;
         }
@@ -292,41 +340,109 @@ __global__ void __launch_bounds__(1024) fft_pass_kernel(PassDesc d, LD ld, Store
     const int tid = threadIdx.x, T = blockDim.x;
     const int L = d.L, lw = d.logW, W = 1 << lw;
     const int E = L << lw;
-    const TileMap m = tile_map(d, blockIdx.y, blockIdx.x);
+    int ta = blockIdx.y, tb = blockIdx.x;
+    if (d.xcd_rows) {
+        // workgroups are dispatched round-robin over the XCDs: give each XCD a contiguous range of
+        // tile rows so that neighbouring rows (which gather from neighbouring spectrum rows) share
+        // one L2
+        // (the grid has kXcds * per rows, per = ceil(tiles_a / kXcds), so every XCD owns exactly
+        // per * nb workgroup slots; rows past tiles_a return at once)
+        const int nb = gridDim.x, na = d.tiles_a;
+        const int lin = blockIdx.y * nb + blockIdx.x;
+        const int xcd = lin % kXcds, slot = lin / kXcds;
+        const int per = (na + kXcds - 1) / kXcds;   // rows per XCD
+        const int row = xcd * per + slot / nb;
+        if (row >= na) return;
+        ta = row;
+        tb = slot % nb;
+    }
+    const TileMap m = tile_map(d, ta, tb);
     const float invL = 1.0f / (float)L;
 
-    // global -> LDS
-    for (int e = tid; e < E; e += T) {
-        int n, w;
-        if (m.in_nfast) { w = fdiv(e, L, invL); n = e - w * L; }
-        else { w = e & (W - 1); n = e >> lw; }
-        cpx<R> v = mk(R(0), R(0));
-        if (w < m.wvalid) v = ld(m.ib + n * m.isn + w * m.isw, n * m.an + w * m.aw + m.a0, m.t0 + w * m.t1);
-        lds[(n << lw) + w] = v;
+    // global -> LDS in rounds of LD::batch elements per thread.  The loads carry no branches
+    // (padding elements load the tile's first element and are zeroed), so all loads of a round are
+    // in flight together before its LDS stores.
+    constexpr int G = LD::batch;
+    for (int r0 = 0; r0 < E; r0 += G * T) {
+        cpx<R> buf[G];
+        int dst[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int e0 = r0 + tid + i * T;
+            const int e = e0 < E ? e0 : 0;
+            int n, w;
+            if (m.in_nfast) { w = fdiv(e, L, invL); n = e - w * L; }
+            else { w = e & (W - 1); n = e >> lw; }
+            const bool valid = e0 < E && w < m.wvalid;
+            const int nn = valid ? n : 0, ww = valid ? w : 0;
+            buf[i] = ld(m.ib + nn * m.isn + ww * m.isw, n * m.an + w * m.aw + m.a0, m.t0 + w * m.t1, valid);
+            dst[i] = e0 < E ? lds_pad((n << lw) + w) : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            if (dst[i] >= 0) lds[dst[i]] = buf[i];
     }
     __syncthreads();
 
     fft_tile<R, MAXE>(lds, d, tw, d.sign, tid, T);
+    int osign = d.sign;
     if (d.chain) {
-        for (int e = tid; e < E; e += T) lds[e] = lds[e] * chainvec[e >> lw] * chainscale;
+        // element-wise multiply by the chain vector (the chirp of Eq. 2), vector loads batched
+        constexpr int GC = MaxElems<R>::value / 2;
+        for (int r0 = 0; r0 < E; r0 += GC * T) {
+            cpx<R> cv[GC];
+#pragma unroll
+            for (int i = 0; i < GC; ++i) {
+                const int e0 = r0 + tid + i * T;
+                const int e = e0 < E ? e0 : 0;
+                const int w = e & (W - 1), n = e >> lw;
+                cv[i] = chainvec[n * m.cn + w * m.cw + m.c0];
+            }
+#pragma unroll
+            for (int i = 0; i < GC; ++i) {
+                const int e = r0 + tid + i * T;
+                if (e < E) {
+                    const int p = lds_pad(e);
+                    lds[p] = lds[p] * cv[i] * chainscale;
+                }
+            }
+        }
         __syncthreads();
-        fft_tile<R, MAXE>(lds, d, tw, -d.sign, tid, T);
+        osign = -d.sign;
+        fft_tile<R, MAXE>(lds, d, tw, osign, tid, T);
     }
 
-    // LDS -> global
-    for (int e = tid; e < E; e += T) {
-        int k, w;
-        if (m.out_nfast) { w = fdiv(e, L, invL); k = e - w * L; }
-        else { w = e & (W - 1); k = e >> lw; }
-        if (w >= m.wvalid) continue;
-        cpx<R> v = lds[(k << lw) + w];
-        if (m.twiddle) {
-            int64_t ex = (int64_t)(m.m0 + w * m.m1) * k % d.Lf;
-            cpx<R> c = twf[ex];
-            if (d.sign > 0) c.y = -c.y;
-            v = v * c;
+    // LDS -> global in rounds: the LDS reads and twiddle loads of a round are issued first (no
+    // branches), then its stores
+    constexpr int GS = MaxElems<R>::value / 2;
+    for (int r0 = 0; r0 < E; r0 += GS * T) {
+        cpx<R> buf[GS];
+        cpx<R> cw[GS];
+#pragma unroll
+        for (int i = 0; i < GS; ++i) {
+            const int e0 = r0 + tid + i * T;
+            const int e = e0 < E ? e0 : 0;
+            int k, w;
+            if (m.out_nfast) { w = fdiv(e, L, invL); k = e - w * L; }
+            else { w = e & (W - 1); k = e >> lw; }
+            buf[i] = lds[lds_pad((k << lw) + w)];
+            // exponent < L1 L2 = Lf: the digit products of a four-step split never wrap
+            const int ex = (m.twiddle && w < m.wvalid) ? (m.m0 + w * m.m1) * k : 0;
+            cw[i] = m.twiddle ? twf[ex] : mk(R(1), R(0));
         }
-        st(m.ob + k * m.osn + w * m.osw, k * m.bn + w * m.bw + m.b0, m.t0 + w * m.t1, v);
+#pragma unroll
+        for (int i = 0; i < GS; ++i) {
+            const int e = r0 + tid + i * T;
+            if (e < E) {
+                int k, w;
+                if (m.out_nfast) { w = fdiv(e, L, invL); k = e - w * L; }
+                else { w = e & (W - 1); k = e >> lw; }
+                cpx<R> c = cw[i];
+                if (osign > 0) c.y = -c.y;
+                if (w < m.wvalid)
+                    st(m.ob + k * m.osn + w * m.osw, k * m.bn + w * m.bw + m.b0, m.t0 + w * m.t1, buf[i] * c);
+            }
+        }
     }
 }
 
@@ -340,8 +456,9 @@ hipError_t launch_pass(const PassDesc& d, const LD& ld, const StorePlain<R>& st,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    size_t shm = (size_t)d.L * d.W * sizeof(cpx<R>);
-    dim3 grid(d.tiles_b, d.tiles_a), block(d.nthreads);
+    size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);
+    const int ga = d.xcd_rows ? kXcds * ((d.tiles_a + kXcds - 1) / kXcds) : d.tiles_a;
+    dim3 grid(d.tiles_b, ga), block(d.nthreads);
     hipLaunchKernelGGL((fft_pass_kernel<R, LD>), grid, block, shm, s, d, ld, st, tw, twf, chainvec, chainscale);
     return hipGetLastError();
 }

@@ -36,6 +36,72 @@ hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ step 2: stretch-gather
+// Pull form of step 2: the stretched spectrum at band sample k' (stretched frequency index
+// k_g = K_c + k' - M/2) is the hologram spectrum Keys-interpolated at the pre-image of k_g.  The map
+// is odd in each axis, so the pre-image of (+-|k_gx|, +-|k_gy|) is (+-P_x, +-P_y) from one table entry.
+// Output carries the (-1)^(k'_x) centring sign of the inverse transform that follows.
+template <typename R>
+__global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
+    // consecutive block rows to one XCD (round-robin dispatch): their stencils share L2 lines
+    const int nb = gridDim.x;
+    const int nrows = (a.nay + blockDim.y - 1) / blockDim.y;
+    const int lin = blockIdx.y * nb + blockIdx.x;
+    const int xcd = lin % kXcds, slot = lin / kXcds;
+    const int per = (nrows + kXcds - 1) / kXcds;
+    const int brow = xcd * per + slot / nb;
+    if (brow >= nrows) return;
+    const int ax = a.ax0 + (slot % nb) * blockDim.x + threadIdx.x;
+    const int ay = a.ay0 + brow * blockDim.y + threadIdx.y;
+    if (ax >= a.ax0 + a.nax || ay >= a.ay0 + a.nay) return;
+    double px, py;
+    bool valid;
+    if (a.nostretch) {
+        valid = ax <= (a.nx >> 1) && ay <= (a.ny >> 1);
+        px = valid ? ax : 0.0;   // masked entries read the centre (in bounds) and are zeroed
+        py = valid ? ay : 0.0;
+    } else {
+        valid = ax <= a.kxt && ay <= a.kyt;
+        const int64_t e = valid ? (int64_t)ay * (a.kxt + 1) + ax : 0;
+        const double tx = a.table[2 * e], ty = a.table[2 * e + 1];
+        valid = valid && tx == tx;
+        // masked entries (NaN in the table, or beyond it) read the spectrum centre and are zeroed:
+        // a NaN coordinate must never reach the index arithmetic
+        px = valid ? tx : 0.0;
+        py = valid ? ty : 0.0;
+    }
+    // the mirrors are interpolated without branches (a masked entry reads the spectrum centre and
+    // is zeroed), so their loads overlap; only the stores are predicated on the band
+    const R scale = valid ? R(1) : R(0);
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+        const int ky = (sy ? -ay : ay) - a.gy0;
+        const bool yin = ky >= 0 && ky < a.my && !(sy && ay == 0);
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+            const int kx = (sx ? -ax : ax) - a.gx0;
+            const bool in = yin && kx >= 0 && kx < a.mx && !(sx && ax == 0);
+            cpx<R> v = keys_spectrum<R>(a.spec, a.nx, a.ny, (sx ? -px : px) + (double)(a.nx >> 1),
+                                        (sy ? -py : py) + (double)(a.ny >> 1));
+            v = v * ((kx & 1) ? -scale : scale);
+            if (in) a.out[(int64_t)ky * a.mx + kx] = v;
+        }
+    }
+}
+
+template <typename R>
+hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st) {
+    dim3 block(64, 4);
+    const int nb = (a.nax + 63) / 64;
+    const int nrows = (a.nay + 3) / 4;
+    const int per = (nrows + kXcds - 1) / kXcds;
+    dim3 grid(nb, kXcds * per);
+    hipLaunchKernelGGL(stretch_gather_kernel<R>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+template hipError_t launch_stretch_gather<float>(const GatherArgs<float>&, hipStream_t);
+template hipError_t launch_stretch_gather<double>(const GatherArgs<double>&, hipStream_t);
+
 // ------------------------------------------------------------ step 5: output gather
 // For output pixel (i, j) at true coordinates (x, y): distorted position (x', y') of Eqs. 17-18
 // (x' = A(x) R^-1/2, y' = B(y) R^-1/2 with per-column / per-row factors A, B), its fractional
@@ -58,34 +124,45 @@ __global__ void output_gather_kernel(OutputArgs<R> a) {
     const double y = a.cy + (double)(i - (a.sy >> 1)) * a.doy;
     double xp, yp;
     if (a.remap) {
-        const double rr = sqrt(x * x + y * y + a.z * a.z);
-        const double rs = 1.0 / sqrt(rr);
-        xp = a.ax[j] * rs;
-        yp = a.by[i] * rs;
+        // R^(-1/2) = r2^(-1/4): float seed, then two Newton steps y <- y (5 - r2 y^4) / 4 in float64
+        const double r2 = x * x + y * y + a.z * a.z;
+        double t = (double)rsqrtf(sqrtf((float)r2));
+        double t2 = t * t;
+        t = t * (5.0 - r2 * (t2 * t2)) * 0.25;
+        t2 = t * t;
+        t = t * (5.0 - r2 * (t2 * t2)) * 0.25;
+        xp = a.ax[j] * t;
+        yp = a.by[i] * t;
     } else {
         xp = x;
         yp = y;
     }
-    const double qx = (xp - a.kcx * a.dfx) / a.dfx + (double)(a.mx >> 1);
-    const double qy = (yp - a.kcy * a.dfy) / a.dfy + (double)(a.my >> 1);
+    const double qx = xp * a.inv_dfx + a.qx0;   // (x' - K_c D_F) / D_F + M/2
+    const double qy = yp * a.inv_dfy + a.qy0;
     const double fx = floor(qx), fy = floor(qy);
     const int ix = (int)fx - 1, iy = (int)fy - 1;
     R wx[4], wy[4];
     keys4<R>(R(qx - fx), wx);
     keys4<R>(R(qy - fy), wy);
+    // taps outside the FrT grid get weight 0 and read a clamped (in-bounds) sample: no branches, so
+    // the 16 loads are in flight together
+    int cols[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = ix + c;
+        wx[c] = (col >= 0 && col < a.mx) ? wx[c] : R(0);
+        cols[c] = min(max(col, 0), a.mx - 1);
+    }
     cpx<R> acc = mk(R(0), R(0));
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int r = iy + b;
-        if (r < 0 || r >= a.my) continue;
-        const cpx<R>* row = a.F + (int64_t)r * a.mx;
+        const R wb = (r >= 0 && r < a.my) ? wy[b] : R(0);
+        const cpx<R>* row = a.F + (int64_t)min(max(r, 0), a.my - 1) * a.mx;
         cpx<R> racc = mk(R(0), R(0));
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = ix + c;
-            if (col >= 0 && col < a.mx) racc = racc + row[col] * wx[c];
-        }
-        acc = acc + racc * wy[b];
+        for (int c = 0; c < 4; ++c) racc = racc + row[cols[c]] * wx[c];
+        acc = acc + racc * wb;
     }
     // outer chirp, phase in float64 reduced by a two-part 2 pi
     double ph = (xp * xp + yp * yp) * a.kz2;
