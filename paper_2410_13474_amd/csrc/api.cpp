@@ -308,6 +308,7 @@ static void chirp_vector(int M, int N, double pitch, double wavelength, double z
 // ---------------------------------------------------------- pass construction
 
 struct Limits {
+    size_t esize;    // bytes per complex element
     int tile_elems;  // LDS tile capacity, elements
     int col_w;       // columns per tile (128-byte runs)
     int max_elems;   // register budget per thread and stage
@@ -322,11 +323,12 @@ static int tile_override() {
 
 static Limits limits_for(size_t esize, int cap) {
     Limits l;
+    l.esize = esize;
     // logical elements whose padded LDS footprint (one pad per 32) fits in 160 KB
     l.tile_elems = (int)(((160 * 1024) / esize - 1) * 32 / 33);
     if (cap > 0) l.tile_elems = std::min(l.tile_elems, cap);
     l.col_w = esize == 8 ? 16 : 8;
-    l.max_elems = esize == 8 ? 32 : 16;
+    l.max_elems = esize == 8 ? 16 : 8;
     return l;
 }
 
@@ -337,12 +339,16 @@ static int ilog2(int w) {
 }
 
 static bool finish_desc(PassDesc& d, const Limits& lim) {
-    if (!factor_radices(d.L, &d.nst, d.rad)) return false;
     d.logW = ilog2(d.W);
     if ((1 << d.logW) != d.W) return false;
     if ((int64_t)d.L * d.W > lim.tile_elems) return false;  // padded LDS footprint within 160 KB
-    d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
-    return d.nthreads > 0;
+    if (!factor_radices(d.L, &d.nst, d.rad, 16)) return false;
+    // prefer one butterfly per thread and stage; else several (long single-pass rows)
+    d.nthreads = pick_threads_one(d.L, d.W, d.nst, d.rad, lim.esize == 8 ? 1024 : 512);
+    d.one_bfly = d.nthreads > 0 ? 1 : 0;
+    if (!d.one_bfly) d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
+    if (d.nthreads <= 0) return false;
+    return pass_offsets_fit(d, (int)lim.esize);
 }
 
 // Split L = L1 L2 so that both passes' tiles (L1 x W and L2 x W) fit, as balanced as possible.
@@ -372,11 +378,8 @@ struct AxisPlan {
     std::vector<PassDesc> passes;  // single: 1 pass; four-step: 2 (plain) or 4 (chain)
 };
 
-// gather_w > 0: the single-pass row transform carries the stretch-gather; its tiles then go to the
-// XCDs in contiguous row ranges so that neighbouring rows (neighbouring spectrum rows) share an L2.
-// In the four-step case the gather runs as a kernel of its own and every pass is plain.
 static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int chain, const Limits& lim,
-                       AxisPlan* ap, int gather_w = 0) {
+                       AxisPlan* ap) {
     ap->passes.clear();
     PassDesc d{};
     d.sign = sign;
@@ -394,11 +397,11 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
             d.chain = chain;
             d.tiles_a = (other + w - 1) / w;
             d.tiles_b = 1;
-            d.xcd_rows = gather_w > 0 ? 1 : 0;
-            if (!finish_desc(d, lim)) return false;
-            ap->single = true;
-            ap->passes.push_back(d);
-            return true;
+            if (finish_desc(d, lim)) {
+                ap->single = true;
+                ap->passes.push_back(d);
+                return true;
+            }  // else more elements per thread than the registers hold: four-step
         }
     } else {
         d.rows = L;
@@ -410,10 +413,11 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
             d.chain = chain;
             d.tiles_a = 1;
             d.tiles_b = (other + d.W - 1) / d.W;
-            if (!finish_desc(d, lim)) return false;
-            ap->single = true;
-            ap->passes.push_back(d);
-            return true;
+            if (finish_desc(d, lim)) {
+                ap->single = true;
+                ap->passes.push_back(d);
+                return true;
+            }
         }
     }
     // four-step: A (over n1) then B (over n2); a chain fuses the first B and the second A
@@ -505,7 +509,7 @@ static uint64_t pass_bytes(const PassDesc& d, size_t esize) { return 2ull * d.ro
 
 template <typename R>
 static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& d, const void* in, void* out,
-                               int load_conj, int load_sign, int store_sign, R store_scale, const cpx<R>* store_vec,
+                               int load_conj, int load_sign, int store_sign, R store_scale,
                                const cpx<R>* chainvec, R chainscale, hipStream_t s) {
     const cpx<R>* tw;
     nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
@@ -516,48 +520,11 @@ static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& 
         if (st != NUFDS_OK) return st;
     }
     LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1)};
-    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_vec, store_sign, store_scale};
+    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_sign, store_scale};
     NUFDS_TRY(timing_begin(p, name, pass_bytes(d, sizeof(cpx<R>)), s));
-    NUFDS_HIP_TRY((launch_pass<R, LoadPlain<R>>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
+    NUFDS_HIP_TRY((launch_pass<R>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
     return timing_end(p, s);
 }
-
-template <typename R>
-static nufds_status_t run_gather_pass(nufds_plan* p, const char* name, const PassDesc& d, void* out, int store_sign,
-                                      R store_scale,
-                                      const cpx<R>* store_vec, const cpx<R>* chainvec, R chainscale,
-                                      hipStream_t s) {
-    const cpx<R>* tw;
-    nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
-    if (st != NUFDS_OK) return st;
-    const cpx<R>* twf = nullptr;
-    if (d.kind == K_ROWA) {
-        st = twiddle_table<R>(p, d.Lf, &twf);
-        if (st != NUFDS_OK) return st;
-    }
-    LoadGather<R> ld;
-    ld.spec = static_cast<const cpx<R>*>(p->spec.p);
-    ld.table = static_cast<const double*>(p->table.p);
-    ld.nx = p->info.nx;
-    ld.ny = p->info.ny;
-    ld.kxt = p->kxt;
-    ld.kyt = p->kyt;
-    ld.mx = p->info.mx;
-    ld.my = p->info.my;
-    ld.kcx = p->info.kcx;
-    ld.kcy = p->info.kcy;
-    ld.nostretch = (p->flags & NUFDS_FLAG_NO_STRETCH) ? 1 : 0;
-    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_vec, store_sign, store_scale};
-    // algorithmic bytes: the quadrant table entries, the spectrum region the band pulls from
-    // (at most the whole spectrum), and the sub-band written once
-    const uint64_t es = sizeof(cpx<R>);
-    const uint64_t mm = (uint64_t)p->info.mx * p->info.my, nn = (uint64_t)p->info.nx * p->info.ny;
-    const uint64_t bytes = p->table.bytes + std::min(mm, nn) * es + mm * es;
-    NUFDS_TRY(timing_begin(p, name, bytes, s));
-    NUFDS_HIP_TRY((launch_pass<R, LoadGather<R>>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
-    return timing_end(p, s);
-}
-
 
 // |k| range of band samples g0 .. g1 (inclusive) along one axis.
 static void abs_range(int g0, int g1, int* lo, int* hi) {
@@ -615,46 +582,46 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
     if (!build_axis(0, nx, ny, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram row length");
     const R sgx = ((nx / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, R(1), s));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, R(1), s));
     }
     if (!build_axis(1, ny, nx, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram column length");
     const R sgy = ((ny / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, R(1), s));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, R(1), s));
     }
 
     // steps 2b-3 along x: stretch-gather, centred IDFT, chirp / M_x, centred DFT (signs cancel to
     // (-1)^k' on input and (-1)^m on output)
     const cpx<R>* cxv = static_cast<const cpx<R>*>(p->chirp_x.p);
     const cpx<R>* cyv = static_cast<const cpx<R>*>(p->chirp_y.p);
-    if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap, 64)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
+    if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
     void* res;
+    // the stretch-gather runs as a kernel of its own (2-D tiles, each quadrant table entry read once)
+    NUFDS_TRY(run_stretch_gather<R>(p, w2, s));
     if (ap.single) {
-        NUFDS_TRY(run_gather_pass<R>(p, "xop_gather", ap.passes[0], w1, 1, R(1), nullptr, cxv, R(1) / R(mx), s));
+        NUFDS_TRY(run_pass<R>(p, "xop", ap.passes[0], w2, w1, 0, 0, 1, R(1), cxv, R(1) / R(mx), s));
         res = w1;
     } else {
-        // the four-step A tile is strided along the row: gather in a kernel of its own first
-        NUFDS_TRY(run_stretch_gather<R>(p, w2, s));
-        NUFDS_TRY(run_pass<R>(p, "xop_a", ap.passes[0], w2, w1, 0, 0, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_ba", ap.passes[1], w1, w2, 0, 0, 0, R(1), nullptr, cxv, R(1) / R(mx), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_b", ap.passes[2], w2, w1, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_a", ap.passes[0], w2, w1, 0, 0, 0, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_ba", ap.passes[1], w1, w2, 0, 0, 0, R(1), cxv, R(1) / R(mx), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_b", ap.passes[2], w2, w1, 0, 0, 1, R(1), nullptr, R(1), s));
         res = w1;
     }
     // and along y
     if (!build_axis(1, my, mx, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), nullptr, cyv, R(1) / R(my), s));
+        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), cyv, R(1) / R(my), s));
     } else {
         void* oth = (res == w1) ? w2 : w1;
-        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), nullptr, cyv, R(1) / R(my), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), cyv, R(1) / R(my), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, R(1), s));
         res = oth;
     }
     p->result = res;
@@ -703,7 +670,7 @@ static nufds_status_t prepare_impl(nufds_plan* p) {
                             {1, g.my, g.mx, g.mx, 1}};
     for (const auto& a : axes) {
         AxisPlan ap;
-        if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap, (a[4] && a[0] == 0) ? 64 : 0))
+        if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap))
             return fail(NUFDS_ERR_UNSUPPORTED, "no FFT pass plan for a transform of length " + std::to_string(a[1]));
         for (const PassDesc& d : ap.passes) {
             const cpx<R>* t;
@@ -731,6 +698,9 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z, view, flags, opt, &g));
     if (g.mx > kMaxLen || g.my > kMaxLen || nx > kMaxLen || ny > kMaxLen || !smooth5(nx) || !smooth5(ny))
         return fail(NUFDS_ERR_UNSUPPORTED, "sizes must be 5-smooth and at most 65536");
+    const int64_t kMaxArray = (int64_t)1 << 31;  // the FFT passes index elements with 32-bit integers
+    if ((int64_t)nx * ny >= kMaxArray || (int64_t)g.mx * g.my >= kMaxArray || (int64_t)g.sx * g.sy >= kMaxArray)
+        return fail(NUFDS_ERR_UNSUPPORTED, "hologram, FrT and output arrays must hold fewer than 2^31 elements");
     nufds_plan* p = new (std::nothrow) nufds_plan();
     if (!p) return fail(NUFDS_ERR_OUT_OF_MEMORY, "host allocation failed");
     p->info = g;

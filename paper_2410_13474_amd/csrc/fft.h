@@ -42,6 +42,7 @@ __host__ __device__ __forceinline__ int lds_elems(int n) { return n + (n >> 5) +
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, each with its own L2
 
 constexpr int kMaxStages = 16;
+constexpr int kMaxBfly = 4;  // butterflies a thread holds in one stage, at most
 
 struct PassDesc {
     int kind;
@@ -58,30 +59,30 @@ struct PassDesc {
     int chain;      // 1: multiply by chain vector, then transform again with the opposite sign
     int tiles_a, tiles_b;
     int xcd_rows;   // 1: hand consecutive tile rows (a) to the same XCD (L2 reuse of gathers)
+    int one_bfly;   // 1: one butterfly per thread per stage (small tiles)
 };
 
-// Elements a thread may hold in registers during one stage.
-template <typename R> struct MaxElems { static constexpr int value = 32; };
-template <> struct MaxElems<double> { static constexpr int value = 16; };
+// Elements a thread may hold in registers during one stage of the several-butterflies variant
+// (with 1024 threads: single-pass tiles of up to 16384 complex64 or 8192 complex128 elements).
+template <typename R> struct MaxElems { static constexpr int value = 16; };
+template <> struct MaxElems<double> { static constexpr int value = 8; };
+// Largest radix of the one-butterfly-per-thread variant.
+template <typename R> struct OneBflyElems { static constexpr int value = 16; };
+template <> struct OneBflyElems<double> { static constexpr int value = 16; };
+// Largest workgroup of the one-butterfly variant (complex128: 512, leaving 256 registers per lane).
+template <typename R> struct OneBflyThreads { static constexpr int value = 1024; };
+template <> struct OneBflyThreads<double> { static constexpr int value = 512; };
 
 // ---------------------------------------------------------------- loads
 
-// in[offset], optionally conjugated, times (-1)^axis, times scale.
+// Source of a pass: in[offset], optionally conjugated, times (-1)^(index along the transformed axis)
+// if sign_axis, times scale.
 template <typename R>
 struct LoadPlain {
-    static constexpr int batch = sizeof(R) == 4 ? 16 : 8;  // loads a thread issues before storing to LDS
     const cpx<R>* in;
     int conj;
     int sign_axis;
     R scale;
-    // Branch-free: the caller passes an in-bounds offset even for padding elements (valid = false),
-    // so that a thread's loads can all be in flight together.
-    __device__ __forceinline__ cpx<R> operator()(int64_t off, int axis, int, bool valid) const {
-        cpx<R> v = in[off];
-        R s = (sign_axis && (axis & 1)) ? -scale : scale;
-        s = valid ? s : R(0);
-        return mk(v.x * s, (conj ? -v.y : v.y) * s);
-    }
 };
 
 // Keys cubic convolution weights (a = -1/2) of the taps at floor-1 .. floor+2 for fraction t.
@@ -124,70 +125,34 @@ __device__ __forceinline__ cpx<R> keys_spectrum(const cpx<R>* __restrict__ spec,
     return acc;
 }
 
-// Step 2 of Sec. 4, pull form: sample (trans, axis) = (k'_y, k'_x) of the sub-band sits at the
-// stretched frequency index k_g = K_c + k' - M/2; its pre-image P (spectral samples from the centre)
-// comes from the quadrant table (odd in each axis), and the spectrum is Keys-interpolated there,
-// periodically.  NaN in the table marks "no pre-image in the propagating disk or outside the band".
-// The result carries the (-1)^(k'_x) of the centred inverse transform that follows.
-template <typename R>
-struct LoadGather {
-    static constexpr int batch = sizeof(R) == 4 ? 2 : 1;  // each element already issues 17 loads
-    const cpx<R>* spec;
-    const double* table;  // (P_x, P_y) pairs, [kyt + 1][kxt + 1]
-    int nx, ny, kxt, kyt;
-    int mx, my, kcx, kcy;
-    int nostretch;
-    __device__ __forceinline__ cpx<R> operator()(int64_t, int axis, int trans, bool valid) const {
-        const int kgx = kcx + axis - (mx >> 1);
-        const int kgy = kcy + trans - (my >> 1);
-        double px, py;
-        if (nostretch) {
-            valid = valid && abs(kgx) <= (nx >> 1) && abs(kgy) <= (ny >> 1);
-            px = valid ? kgx : 0;   // masked samples read the centre (in bounds) and are zeroed
-            py = valid ? kgy : 0;
-        } else {
-            const int ax = abs(kgx), ay = abs(kgy);
-            valid = valid && ax <= kxt && ay <= kyt;
-            const int64_t e = valid ? (int64_t)ay * (kxt + 1) + ax : 0;
-            const double tx = table[2 * e], ty = table[2 * e + 1];
-            valid = valid && tx == tx;
-            px = valid ? (kgx < 0 ? -tx : tx) : 0.0;
-            py = valid ? (kgy < 0 ? -ty : ty) : 0.0;
-        }
-        const cpx<R> acc = keys_spectrum<R>(spec, nx, ny, px + (double)(nx >> 1), py + (double)(ny >> 1));
-        const R s = valid ? ((axis & 1) ? R(-1) : R(1)) : R(0);
-        return acc * s;
-    }
-};
-
 // ---------------------------------------------------------------- stores
 
-// out[offset] = v * (vec ? vec[axis] : 1) * scale * ((-1)^axis if sign_axis).
+// Destination of a pass: out[offset] = v * scale * ((-1)^(index along the axis) if sign_axis).
 template <typename R>
 struct StorePlain {
     cpx<R>* out;
-    const cpx<R>* vec;
     int sign_axis;
     R scale;
-    __device__ __forceinline__ void operator()(int64_t off, int axis, int, cpx<R> v) const {
-        if (vec) v = v * vec[axis];
-        R s = (sign_axis && (axis & 1)) ? -scale : scale;
-        out[off] = v * s;
-    }
 };
 
 // ---------------------------------------------------------------- host side
 
 struct FftTables;  // per-length twiddle tables, owned by a plan
 
-template <typename R, typename LD>
-hipError_t launch_pass(const PassDesc& d, const LD& ld, const StorePlain<R>& st, const cpx<R>* tw,
+template <typename R>
+hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                        const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s);
 
-// Radix sequence of a 5-smooth length (16, 8, 4, 2 first, then 5, 3); false if not 5-smooth.
-bool factor_radices(int L, int* nst, int* rad);
+// Radix sequence of a 5-smooth length with the fewest stages (radices 2-6, 8-10, 12, 15, 16 up to
+// max_radix); false if there is none.
+bool factor_radices(int L, int* nst, int* rad, int max_radix);
+
+// Whether the 32-bit per-lane offsets of the pass's global accesses can address its tiles.
+bool pass_offsets_fit(const PassDesc& d, int esize);
 
 // Threads per block such that no thread holds more than the register budget in any stage.
 int pick_threads(int L, int W, int nst, const int* rad, int max_elems);
+// Threads for one butterfly per thread per stage, or -1 if a stage has more than max_threads butterflies.
+int pick_threads_one(int L, int W, int nst, const int* rad, int max_threads);
 
 }  // namespace nufds

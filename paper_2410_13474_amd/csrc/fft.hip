@@ -2,6 +2,9 @@
 #include "fft.h"
 
 #include <cmath>
+#include <utility>
+#include <vector>
+#include <algorithm>
 
 namespace nufds {
 
@@ -127,6 +130,105 @@ struct SmallDft<R, 16> {
     }
 };
 
+// ---- composite radices R = A B built in registers from the small DFTs above.
+// Compile-time twiddles: cos / sin of 2 pi m / R by an octant reduction and a Taylor series
+// (|x| <= pi / 4, 12 terms: below double rounding).
+constexpr double kTwoPi = 6.28318530717958647692;
+
+constexpr double taylor_sin(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k < 12; ++k) {
+        term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double taylor_cos(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 12; ++k) {
+        term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+
+// cos and sin of 2 pi m / R
+constexpr double turn_cos(int m, int R) {
+    const int mm = ((m % R) + R) % R;
+    const double f = (double)mm / (double)R;
+    const int q = (int)(4.0 * f + 0.5);
+    const double x = kTwoPi * (f - 0.25 * q);
+    return (q % 4 == 0) ? taylor_cos(x) : (q % 4 == 1) ? -taylor_sin(x) : (q % 4 == 2) ? -taylor_cos(x) : taylor_sin(x);
+}
+constexpr double turn_sin(int m, int R) {
+    const int mm = ((m % R) + R) % R;
+    const double f = (double)mm / (double)R;
+    const int q = (int)(4.0 * f + 0.5);
+    const double x = kTwoPi * (f - 0.25 * q);
+    return (q % 4 == 0) ? taylor_sin(x) : (q % 4 == 1) ? taylor_cos(x) : (q % 4 == 2) ? -taylor_sin(x) : -taylor_cos(x);
+}
+
+template <int M, int R>
+struct TwC {
+    static constexpr double c = turn_cos(M, R);
+    static constexpr double s = turn_sin(M, R);
+};
+
+// R = A B with n = n2 + B n1, k = k1 + A k2: A-point DFTs over n1 in place (y[n2][k1] at v[n2 + B k1]),
+// twiddle w_R^(n2 k1), B-point DFTs over n2 in place; X_(k1 + A k2) ends in v[B k1 + k2].
+// A and B are 2, 3, 4 or 5 (identity output order).
+template <typename R, int A, int B>
+struct Composite {
+    static constexpr int RAD = A * B;
+    __device__ static constexpr int perm(int t) { return B * (t % A) + t / A; }
+
+    template <int N2, int K1>
+    __device__ __forceinline__ static void twiddle(cpx<R>* v, int sign) {
+        if constexpr (N2 * K1 != 0) {
+            const R c = R(TwC<N2 * K1, RAD>::c);
+            const R s = R(TwC<N2 * K1, RAD>::s) * R(sign);
+            v[N2 + B * K1] = v[N2 + B * K1] * mk(c, s);
+        }
+    }
+    template <int N2>
+    __device__ __forceinline__ static void inner(cpx<R>* v, int sign) {
+        cpx<R> t[A];
+#pragma unroll
+        for (int i = 0; i < A; ++i) t[i] = v[N2 + B * i];
+        SmallDft<R, A>::run(t, sign);
+#pragma unroll
+        for (int i = 0; i < A; ++i) v[N2 + B * i] = t[i];
+        twiddle_row<N2>(v, sign, std::make_integer_sequence<int, A>{});
+    }
+    template <int N2, int... K1>
+    __device__ __forceinline__ static void twiddle_row(cpx<R>* v, int sign, std::integer_sequence<int, K1...>) {
+        (twiddle<N2, K1>(v, sign), ...);
+    }
+    template <int... N2>
+    __device__ __forceinline__ static void inners(cpx<R>* v, int sign, std::integer_sequence<int, N2...>) {
+        (inner<N2>(v, sign), ...);
+    }
+    __device__ __forceinline__ static void run(cpx<R>* v, int sign) {
+        inners(v, sign, std::make_integer_sequence<int, B>{});
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            cpx<R> t[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) t[i] = v[B * k1 + i];
+            SmallDft<R, B>::run(t, sign);
+#pragma unroll
+            for (int i = 0; i < B; ++i) v[B * k1 + i] = t[i];
+        }
+    }
+};
+
+template <typename R> struct SmallDft<R, 6> : Composite<R, 3, 2> {};
+template <typename R> struct SmallDft<R, 9> : Composite<R, 3, 3> {};
+template <typename R> struct SmallDft<R, 10> : Composite<R, 5, 2> {};
+template <typename R> struct SmallDft<R, 12> : Composite<R, 4, 3> {};
+template <typename R> struct SmallDft<R, 15> : Composite<R, 5, 3> {};
+
 // q = j / n for 0 <= j < 2^24 through a float reciprocal, corrected to exact.
 __device__ __forceinline__ int fdiv(int j, int n, float inv) {
     int q = (int)((float)j * inv);
@@ -145,86 +247,29 @@ __device__ __forceinline__ void twiddle_powers(cpx<R> w, cpx<R>* wp) {
     for (int t = 2; t < RAD; ++t) wp[t] = wp[t / 2] * wp[t - t / 2];
 }
 
-// One Stockham stage of radix RAD over the LDS tile (Govindaraju et al., SC 2008 formulation):
-// butterfly j reads x[j + t L/RAD], twiddles by w_(Ns RAD)^(t k), k = j mod Ns, and writes
-// (j / Ns) Ns RAD + k + t Ns.  All reads happen before the barrier, all writes after.
-template <typename R, int RAD, int MAXE>
-__device__ __forceinline__ void fft_stage(cpx<R>* lds, int L, int lw, int Ns, const cpx<R>* __restrict__ tw,
-                                          int sign, int tid, int T) {
-    constexpr int NB = MAXE / RAD;
-    // per-stage opaque copy of the thread index: keeps the compiler from hoisting every
-    // butterfly's LDS addresses out of the stage loop (they would stay live across all stages)
-    int tid_s = tid;
-    asm volatile("" : "+v"(tid_s));
-    const int W = 1 << lw;
-    const int LR = L / RAD;
-    const int B = LR << lw;
-    const int tstride = L / (Ns * RAD);
-    const float inv = 1.0f / (float)Ns;
-    cpx<R> v[NB][RAD];
-    cpx<R> cw[NB];
-    // reads: LDS inputs and the butterfly's twiddle, all issued before the barrier and without
-    // branches (butterflies past B read butterfly 0 and are not written back)
+// v[t] *= w^t for t = 1 .. RAD-1.  Up to radix 8 the powers come from a product tree; above,
+// w^t = (w^4)^(t/4) w^(t%4), which keeps 4 + ceil(RAD/4) values live instead of RAD (a few
+// more roundings, ~1e-6 in float32, ~1e-15 in float64).
+template <typename R, int RAD>
+__device__ __forceinline__ void apply_twiddles(cpx<R>* v, cpx<R> w) {
+    if constexpr (RAD <= 8) {
+        cpx<R> wp[RAD];
+        twiddle_powers<R, RAD>(w, wp);
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b0 = tid_s + i * T;
-        const int b = b0 < B ? b0 : 0;
-        const int w = b & (W - 1), j = b >> lw;
-        const int q = fdiv(j, Ns, inv);
-        const int k = j - q * Ns;
-        cw[i] = tw[k * tstride];
+        for (int t = 1; t < RAD; ++t) v[t] = v[t] * wp[t];
+    } else {
+        cpx<R> lo[4];
+        lo[0] = mk(R(1), R(0));
+        lo[1] = w;
+        lo[2] = w * w;
+        lo[3] = lo[2] * w;
+        const cpx<R> w4 = lo[2] * lo[2];
+        cpx<R> hi = mk(R(1), R(0));
 #pragma unroll
-        for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_pad(((j + t * LR) << lw) + w)];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = tid_s + i * T;
-        if (b < B) {
-            const int w = b & (W - 1), j = b >> lw;
-            const int q = fdiv(j, Ns, inv);
-            const int k = j - q * Ns;
-            cpx<R> c = cw[i];
-            if (sign > 0) c.y = -c.y;
-            if (sizeof(R) == 4) {
-                cpx<R> wp[RAD];
-                twiddle_powers<R, RAD>(c, wp);
-#pragma unroll
-                for (int t = 1; t < RAD; ++t) v[i][t] = v[i][t] * wp[t];
-            } else {
-                // float64: a running product (<= RAD - 2 roundings, ~1e-15) keeps registers free
-                cpx<R> p = c;
-#pragma unroll
-                for (int t = 1; t < RAD; ++t) {
-                    v[i][t] = v[i][t] * p;
-                    if (t + 1 < RAD) p = p * c;
-                }
-            }
-            SmallDft<R, RAD>::run(v[i], sign);
-            const int base = q * Ns * RAD + k;
-#pragma unroll
-            for (int t = 0; t < RAD; ++t)
-                lds[lds_pad(((base + t * Ns) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)];
+        for (int t = 1; t < RAD; ++t) {
+            if (t % 4 == 0) hi = (t == 4) ? w4 : hi * w4;
+            v[t] = v[t] * ((t % 4) ? hi * lo[t % 4] : hi);
         }
-    }
-    __syncthreads();
-}
-
-template <typename R, int MAXE>
-__device__ __forceinline__ void fft_tile(cpx<R>* lds, const PassDesc& d, const cpx<R>* __restrict__ tw, int sign,
-                                         int tid, int T) {
-    int Ns = 1;
-    for (int s = 0; s < d.nst; ++s) {
-        const int r = d.rad[s];
-        switch (r) {
-            case 16: fft_stage<R, 16, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-            case 8: fft_stage<R, 8, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-            case 4: fft_stage<R, 4, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-            case 2: fft_stage<R, 2, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-            case 5: fft_stage<R, 5, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-            default: fft_stage<R, 3, MAXE>(lds, d.L, d.logW, Ns, tw, sign, tid, T); break;
-        }
-        Ns *= r;
     }
 }
 
@@ -232,14 +277,16 @@ __device__ __forceinline__ void fft_tile(cpx<R>* lds, const PassDesc& d, const c
 // transformed axis is n an + w aw + a0 (input) or k bn + w bw + b0 (output); the chain multiply of a
 // fused pass reads the vector at n cn + w cw + c0; the transverse index is t0 + w t1; the four-step
 // twiddle exponent of the store is (m0 + w m1) k.
+__host__ __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
 struct TileMap {
-    int64_t ib, isn, isw, ob, osn, osw;
+    int ib, isn, isw, ob, osn, osw;  // element offsets: every array holds fewer than 2^31 elements
     int an, aw, a0, bn, bw, b0, cn, cw, c0, t0, t1, m0, m1;
     int wvalid;
     bool in_nfast, out_nfast, twiddle;
 };
 
-__device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
+__host__ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
     TileMap m;
     const int W = d.W;
     m.twiddle = false;
@@ -248,27 +295,27 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
     switch (d.kind) {
         case K_ROW1: {
             int r0 = a * W;
-            m.wvalid = min(W, d.rows - r0);
-            m.ib = r0 * d.in_pitch; m.isn = 1; m.isw = d.in_pitch;
-            m.ob = r0 * d.out_pitch; m.osn = 1; m.osw = d.out_pitch;
+            m.wvalid = imin(W, d.rows - r0);
+            m.ib = r0 * (int)d.in_pitch; m.isn = 1; m.isw = (int)d.in_pitch;
+            m.ob = r0 * (int)d.out_pitch; m.osn = 1; m.osw = (int)d.out_pitch;
             m.an = 1; m.aw = 0; m.a0 = 0; m.bn = 1; m.bw = 0; m.b0 = 0; m.t0 = r0; m.t1 = 1;
             m.in_nfast = m.out_nfast = true;
             break;
         }
         case K_COL1: {
             int c0 = b * W;
-            m.wvalid = min(W, d.cols - c0);
-            m.ib = c0; m.isn = d.in_pitch; m.isw = 1;
-            m.ob = c0; m.osn = d.out_pitch; m.osw = 1;
+            m.wvalid = imin(W, d.cols - c0);
+            m.ib = c0; m.isn = (int)d.in_pitch; m.isw = 1;
+            m.ob = c0; m.osn = (int)d.out_pitch; m.osw = 1;
             m.an = 1; m.aw = 0; m.a0 = 0; m.bn = 1; m.bw = 0; m.b0 = 0; m.t0 = c0; m.t1 = 1;
             m.in_nfast = m.out_nfast = false;
             break;
         }
         case K_ROWA: {
             int row = a, n20 = b * W;
-            m.wvalid = min(W, d.L2 - n20);
-            m.ib = row * d.in_pitch + n20; m.isn = d.L2; m.isw = 1;
-            m.ob = row * d.out_pitch + n20; m.osn = d.L2; m.osw = 1;
+            m.wvalid = imin(W, d.L2 - n20);
+            m.ib = row * (int)d.in_pitch + n20; m.isn = d.L2; m.isw = 1;
+            m.ob = row * (int)d.out_pitch + n20; m.osn = d.L2; m.osw = 1;
             m.an = d.L2; m.aw = 1; m.a0 = n20; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = row; m.t1 = 0;
             m.twiddle = true; m.m0 = n20; m.m1 = 1;
             m.in_nfast = m.out_nfast = false;
@@ -276,9 +323,9 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
         }
         case K_ROWB: {
             int row = a, k10 = b * W;
-            m.wvalid = min(W, d.L1 - k10);
-            m.ib = row * d.in_pitch + (int64_t)k10 * d.L2; m.isn = 1; m.isw = d.L2;
-            m.ob = row * d.out_pitch + k10; m.osn = d.L1; m.osw = 1;
+            m.wvalid = imin(W, d.L1 - k10);
+            m.ib = row * (int)d.in_pitch + k10 * d.L2; m.isn = 1; m.isw = d.L2;
+            m.ob = row * (int)d.out_pitch + k10; m.osn = d.L1; m.osw = 1;
             m.an = 0; m.aw = 0; m.a0 = 0; m.bn = d.L1; m.bw = 1; m.b0 = k10; m.t0 = row; m.t1 = 0;
             m.in_nfast = true; m.out_nfast = false;
             break;
@@ -286,9 +333,9 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
         case K_ROWBA: {
             // input as ROWB (k1 = k10 + w, n over k2); output position q1 L1 + k1 with twiddle w^(k1 q1)
             int row = a, k10 = b * W;
-            m.wvalid = min(W, d.L1 - k10);
-            m.ib = row * d.in_pitch + (int64_t)k10 * d.L2; m.isn = 1; m.isw = d.L2;
-            m.ob = row * d.out_pitch + k10; m.osn = d.L1; m.osw = 1;
+            m.wvalid = imin(W, d.L1 - k10);
+            m.ib = row * (int)d.in_pitch + k10 * d.L2; m.isn = 1; m.isw = d.L2;
+            m.ob = row * (int)d.out_pitch + k10; m.osn = d.L1; m.osw = 1;
             m.an = 0; m.aw = 0; m.a0 = 0; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = row; m.t1 = 0;
             m.cn = d.L1; m.cw = 1; m.c0 = k10;
             m.twiddle = true; m.m0 = k10; m.m1 = 1;
@@ -297,9 +344,9 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
         }
         case K_COLA: {
             int n2 = a, c0 = b * W;
-            m.wvalid = min(W, d.cols - c0);
-            m.ib = n2 * d.in_pitch + c0; m.isn = (int64_t)d.L2 * d.in_pitch; m.isw = 1;
-            m.ob = n2 * d.out_pitch + c0; m.osn = (int64_t)d.L2 * d.out_pitch; m.osw = 1;
+            m.wvalid = imin(W, d.cols - c0);
+            m.ib = n2 * (int)d.in_pitch + c0; m.isn = d.L2 * (int)d.in_pitch; m.isw = 1;
+            m.ob = n2 * (int)d.out_pitch + c0; m.osn = d.L2 * (int)d.out_pitch; m.osw = 1;
             m.an = d.L2; m.aw = 0; m.a0 = n2; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = c0; m.t1 = 1;
             m.twiddle = true; m.m0 = n2; m.m1 = 0;
             m.in_nfast = m.out_nfast = false;
@@ -307,18 +354,18 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
         }
         case K_COLB: {
             int k1 = a, c0 = b * W;
-            m.wvalid = min(W, d.cols - c0);
-            m.ib = (int64_t)k1 * d.L2 * d.in_pitch + c0; m.isn = d.in_pitch; m.isw = 1;
-            m.ob = k1 * d.out_pitch + c0; m.osn = (int64_t)d.L1 * d.out_pitch; m.osw = 1;
+            m.wvalid = imin(W, d.cols - c0);
+            m.ib = k1 * d.L2 * (int)d.in_pitch + c0; m.isn = (int)d.in_pitch; m.isw = 1;
+            m.ob = k1 * (int)d.out_pitch + c0; m.osn = d.L1 * (int)d.out_pitch; m.osw = 1;
             m.an = 0; m.aw = 0; m.a0 = 0; m.bn = d.L1; m.bw = 0; m.b0 = k1; m.t0 = c0; m.t1 = 1;
             m.in_nfast = m.out_nfast = false;
             break;
         }
         default: {  // K_COLBA: input as COLB, output row q1 L1 + k1 with twiddle w^(k1 q1)
             int k1 = a, c0 = b * W;
-            m.wvalid = min(W, d.cols - c0);
-            m.ib = (int64_t)k1 * d.L2 * d.in_pitch + c0; m.isn = d.in_pitch; m.isw = 1;
-            m.ob = k1 * d.out_pitch + c0; m.osn = (int64_t)d.L1 * d.out_pitch; m.osw = 1;
+            m.wvalid = imin(W, d.cols - c0);
+            m.ib = k1 * d.L2 * (int)d.in_pitch + c0; m.isn = (int)d.in_pitch; m.isw = 1;
+            m.ob = k1 * (int)d.out_pitch + c0; m.osn = d.L1 * (int)d.out_pitch; m.osw = 1;
             m.an = 0; m.aw = 0; m.a0 = 0; m.bn = 0; m.bw = 0; m.b0 = 0; m.t0 = c0; m.t1 = 1;
             m.cn = d.L1; m.cw = 0; m.c0 = k1;
             m.twiddle = true; m.m0 = k1; m.m1 = 0;
@@ -329,14 +376,204 @@ __device__ __forceinline__ TileMap tile_map(const PassDesc& d, int a, int b) {
     return m;
 }
 
-template <typename R, typename LD>
-__global__ void __launch_bounds__(1024) fft_pass_kernel(PassDesc d, LD ld, StorePlain<R> st,
+// Global accesses as a wave-uniform base plus a 32-bit per-lane byte offset.  The base is pinned to
+// scalar registers (it is uniform; the read-first-lane only tells the compiler so), which gives the
+// scalar-base form of the load and store: one address register per lane, shared by every element
+// of a butterfly, instead of a 64-bit address per element.
+typedef __attribute__((address_space(1))) char gbyte;
+
+template <typename T>
+__device__ __forceinline__ gbyte* uniform_base(const T* p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (gbyte*)(((uint64_t)hi << 32) | lo);
+}
+template <typename R>
+using vec2 = R __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ cpx<R> load_at(gbyte* base, uint32_t off) {
+    const vec2<R> v = *reinterpret_cast<const vec2<R> __attribute__((address_space(1)))*>(base + off);
+    return mk(R(v.x), R(v.y));
+}
+template <typename R>
+__device__ __forceinline__ void store_at(gbyte* base, uint32_t off, cpx<R> v) {
+    vec2<R> w;
+    w.x = v.x;
+    w.y = v.y;
+    *reinterpret_cast<vec2<R> __attribute__((address_space(1)))*>(base + off) = w;
+}
+
+// Butterflies a thread holds in one stage of radix RAD (the host sizes its thread count by the same rule).
+template <int RAD, int MAXE, int NBMAX>
+struct StageNb {
+    static constexpr int a = MAXE / RAD < NBMAX ? MAXE / RAD : NBMAX;
+    static constexpr int value = a < kMaxBfly ? a : kMaxBfly;
+};
+
+// One Stockham stage of radix RAD (Govindaraju et al., SC 2008 formulation): butterfly j reads
+// x[j + t L/RAD], twiddles by w_(Ns RAD)^(t k), k = j mod Ns, and writes (j / Ns) Ns RAD + k + t Ns.
+// The first stage of a pass reads its inputs from global memory and the last stage writes its
+// outputs to global memory (with the four-step twiddle of A passes), so the tile crosses LDS only
+// between stages.  Element n = j + t L/RAD of lane (j, w) sits at a wave-uniform base (tile origin plus
+// t L/RAD rows) plus a per-lane offset that is the same for every t.  Threads take butterflies in the
+// order that makes their global accesses contiguous (j fastest for transforms that run along memory,
+// w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
+// precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
+template <typename R, int RAD, int MAXE, int NBMAX, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
+                                          const StorePlain<R>& st, const cpx<R>* __restrict__ tw,
+                                          const cpx<R>* __restrict__ twf, int Ns, int sign, int tid, int T) {
+    constexpr int NB = StageNb<RAD, MAXE, NBMAX>::value;
+    constexpr uint32_t ES = sizeof(cpx<R>);
+    // per-stage opaque copy of the thread index: keeps the compiler from hoisting every
+    // butterfly's addresses out of the stage loop (they would stay live across all stages)
+    int tid_s = tid;
+    asm volatile("" : "+v"(tid_s));
+    // the same for the tile origins, which would otherwise pin every stage's global bases in
+    // scalar registers for the whole kernel
+    int ib_s = m.ib, ob_s = m.ob;
+    asm volatile("" : "+s"(ib_s), "+s"(ob_s));
+    const int L = d.L, lw = d.logW, W = 1 << lw;
+    const int LR = L / RAD;
+    const int B = LR << lw;
+    const int tstride = L / (Ns * RAD);
+    const float invNs = 1.0f / (float)Ns;
+    const float invLR = 1.0f / (float)LR;
+    const bool jfast = FIRST ? m.in_nfast : (LAST ? m.out_nfast : (W == 1));
+    cpx<R> v[NB][RAD];
+    cpx<R> cw[NB];
+    cpx<R> c4a[NB], c4b[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b0 = tid_s + i * T;
+        const int b = b0 < B ? b0 : 0;
+        int j, w;
+        if (jfast) { w = fdiv(b, LR, invLR); j = b - w * LR; }
+        else { w = b & (W - 1); j = b >> lw; }
+        const int q = fdiv(j, Ns, invNs);
+        const int k = j - q * Ns;
+        if (!FIRST) cw[i] = load_at<R>(uniform_base(tw), (uint32_t)(k * tstride) * ES);
+        if (FIRST) {
+            const bool valid = b0 < B && w < m.wvalid;
+            const uint32_t lo = valid ? (uint32_t)(j * m.isn + w * m.isw) * ES : 0u;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t)
+                v[i][t] = load_at<R>(uniform_base(ld.in + ((int64_t)ib_s + (int64_t)(t * LR) * m.isn)), lo);
+        } else {
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_pad(((j + t * LR) << lw) + w)];
+        }
+        if (LAST && m.twiddle) {
+            // outputs sit at pos = j + t LR (Ns = LR in the last stage); the four-step twiddle
+            // w_Lf^(e pos) = w^(e j) (w^(e LR))^t with e = m0 + w m1; e pos < Lf never wraps
+            const int e = (w < m.wvalid) ? m.m0 + w * m.m1 : 0;
+            c4a[i] = load_at<R>(uniform_base(twf), (uint32_t)(e * j) * ES);
+            c4b[i] = load_at<R>(uniform_base(twf), (uint32_t)(e * LR) * ES);
+        }
+    }
+    if (!FIRST && !LAST) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid_s + i * T;
+        if (b < B) {
+            int j, w;
+            if (jfast) { w = fdiv(b, LR, invLR); j = b - w * LR; }
+            else { w = b & (W - 1); j = b >> lw; }
+            const int q = fdiv(j, Ns, invNs);
+            const int k = j - q * Ns;
+            if (FIRST) {
+                // fused load work: conjugation, (-1)^(axis index) centring, scale; padding lanes give 0
+                const R sc = (w < m.wvalid) ? ld.scale : R(0);
+                const int par = (j * m.an + w * m.aw + m.a0) & 1;
+#pragma unroll
+                for (int t = 0; t < RAD; ++t) {
+                    const bool flip = ld.sign_axis && ((par + t * LR * m.an) & 1);
+                    const R f = flip ? -sc : sc;
+                    v[i][t] = mk(v[i][t].x * f, (ld.conj ? -v[i][t].y : v[i][t].y) * f);
+                }
+            } else {
+                cpx<R> c = cw[i];
+                if (sign > 0) c.y = -c.y;
+                if (sizeof(R) == 4) {
+                    apply_twiddles<R, RAD>(v[i], c);
+                } else {
+                    // float64: a running product (<= RAD - 2 roundings, ~1e-15) keeps registers free
+                    cpx<R> p = c;
+#pragma unroll
+                    for (int t = 1; t < RAD; ++t) {
+                        v[i][t] = v[i][t] * p;
+                        if (t + 1 < RAD) p = p * c;
+                    }
+                }
+            }
+            SmallDft<R, RAD>::run(v[i], sign);
+            if (LAST) {
+                // pos = j + t LR
+                if (w < m.wvalid) {
+                    cpx<R> tf = mk(R(1), R(0)), step = mk(R(1), R(0));
+                    if (m.twiddle) {
+                        tf = c4a[i];
+                        step = c4b[i];
+                        if (sign > 0) {
+                            tf.y = -tf.y;
+                            step.y = -step.y;
+                        }
+                    }
+                    const uint32_t lo = (uint32_t)(j * m.osn + w * m.osw) * ES;
+                    const int par = (j * m.bn + w * m.bw + m.b0) & 1;
+#pragma unroll
+                    for (int t = 0; t < RAD; ++t) {
+                        const bool flip = st.sign_axis && ((par + t * LR * m.bn) & 1);
+                        const R f = flip ? -st.scale : st.scale;
+                        store_at<R>(uniform_base(st.out + ((int64_t)ob_s + (int64_t)(t * LR) * m.osn)), lo,
+                                 v[i][SmallDft<R, RAD>::perm(t)] * tf * f);
+                        tf = tf * step;
+                    }
+                }
+            } else {
+                const int base = q * Ns * RAD + k;
+#pragma unroll
+                for (int t = 0; t < RAD; ++t)
+                    lds[lds_pad(((base + t * Ns) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)];
+            }
+        }
+    }
+    if (!LAST) __syncthreads();
+}
+
+template <typename R, int MAXE, int NBMAX, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
+                                            const StorePlain<R>& st, const cpx<R>* __restrict__ tw,
+                                            const cpx<R>* __restrict__ twf, int Ns, int sign, int tid, int T) {
+#define NUFDS_STAGE(RR)                                                                             \
+    if constexpr ((RR) <= MAXE)                                                                     \
+        fft_stage<R, RR, MAXE, NBMAX, FIRST, LAST>(lds, d, m, ld, st, tw, twf, Ns, sign, tid, T)
+    switch (r) {
+        case 16: NUFDS_STAGE(16); break;
+        case 8: NUFDS_STAGE(8); break;
+        case 4: NUFDS_STAGE(4); break;
+        case 2: NUFDS_STAGE(2); break;
+        case 5: NUFDS_STAGE(5); break;
+        case 3: NUFDS_STAGE(3); break;
+        case 6: NUFDS_STAGE(6); break;
+        case 9: NUFDS_STAGE(9); break;
+        case 10: NUFDS_STAGE(10); break;
+        case 12: NUFDS_STAGE(12); break;
+        default: NUFDS_STAGE(15); break;
+    }
+#undef NUFDS_STAGE
+}
+
+// NBMAX: butterflies a thread holds per stage.  NBMAX = 1 is the small-tile variant (one butterfly
+// per thread, more threads, fewer live registers); the other variant serves long single-pass rows.
+template <typename R, int MAXE, int NBMAX, int MAXT>
+__global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
                                                         const cpx<R>* __restrict__ tw,
                                                         const cpx<R>* __restrict__ twf,
                                                         const cpx<R>* __restrict__ chainvec, R chainscale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    constexpr int MAXE = MaxElems<R>::value;
     const int tid = threadIdx.x, T = blockDim.x;
     const int L = d.L, lw = d.logW, W = 1 << lw;
     const int E = L << lw;
@@ -357,35 +594,21 @@ __global__ void __launch_bounds__(1024) fft_pass_kernel(PassDesc d, LD ld, Store
         tb = slot % nb;
     }
     const TileMap m = tile_map(d, ta, tb);
-    const float invL = 1.0f / (float)L;
+    const int nst = d.nst;
 
-    // global -> LDS in rounds of LD::batch elements per thread.  The loads carry no branches
-    // (padding elements load the tile's first element and are zeroed), so all loads of a round are
-    // in flight together before its LDS stores.
-    constexpr int G = LD::batch;
-    for (int r0 = 0; r0 < E; r0 += G * T) {
-        cpx<R> buf[G];
-        int dst[G];
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const int e0 = r0 + tid + i * T;
-            const int e = e0 < E ? e0 : 0;
-            int n, w;
-            if (m.in_nfast) { w = fdiv(e, L, invL); n = e - w * L; }
-            else { w = e & (W - 1); n = e >> lw; }
-            const bool valid = e0 < E && w < m.wvalid;
-            const int nn = valid ? n : 0, ww = valid ? w : 0;
-            buf[i] = ld(m.ib + nn * m.isn + ww * m.isw, n * m.an + w * m.aw + m.a0, m.t0 + w * m.t1, valid);
-            dst[i] = e0 < E ? lds_pad((n << lw) + w) : -1;
-        }
-#pragma unroll
-        for (int i = 0; i < G; ++i)
-            if (dst[i] >= 0) lds[dst[i]] = buf[i];
+    // transform 1: stage 0 reads global memory; the last stage writes global memory unless a
+    // second transform follows in this pass
+    int Ns = 1;
+    const bool one = !d.chain;
+    for (int s = 0; s < nst; ++s) {
+        const int r = d.rad[s];
+        const bool first = s == 0, last = one && s == nst - 1;
+        if (first && last) fft_stage_r<R, MAXE, NBMAX, true, true>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
+        else if (first) fft_stage_r<R, MAXE, NBMAX, true, false>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
+        else if (last) fft_stage_r<R, MAXE, NBMAX, false, true>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
+        else fft_stage_r<R, MAXE, NBMAX, false, false>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
+        Ns *= r;
     }
-    __syncthreads();
-
-    fft_tile<R, MAXE>(lds, d, tw, d.sign, tid, T);
-    int osign = d.sign;
     if (d.chain) {
         // element-wise multiply by the chain vector (the chirp of Eq. 2), vector loads batched
         constexpr int GC = MaxElems<R>::value / 2;
@@ -408,89 +631,97 @@ __global__ void __launch_bounds__(1024) fft_pass_kernel(PassDesc d, LD ld, Store
             }
         }
         __syncthreads();
-        osign = -d.sign;
-        fft_tile<R, MAXE>(lds, d, tw, osign, tid, T);
-    }
-
-    // LDS -> global in rounds: the LDS reads and twiddle loads of a round are issued first (no
-    // branches), then its stores
-    constexpr int GS = MaxElems<R>::value / 2;
-    for (int r0 = 0; r0 < E; r0 += GS * T) {
-        cpx<R> buf[GS];
-        cpx<R> cw[GS];
-#pragma unroll
-        for (int i = 0; i < GS; ++i) {
-            const int e0 = r0 + tid + i * T;
-            const int e = e0 < E ? e0 : 0;
-            int k, w;
-            if (m.out_nfast) { w = fdiv(e, L, invL); k = e - w * L; }
-            else { w = e & (W - 1); k = e >> lw; }
-            buf[i] = lds[lds_pad((k << lw) + w)];
-            // exponent < L1 L2 = Lf: the digit products of a four-step split never wrap
-            const int ex = (m.twiddle && w < m.wvalid) ? (m.m0 + w * m.m1) * k : 0;
-            cw[i] = m.twiddle ? twf[ex] : mk(R(1), R(0));
-        }
-#pragma unroll
-        for (int i = 0; i < GS; ++i) {
-            const int e = r0 + tid + i * T;
-            if (e < E) {
-                int k, w;
-                if (m.out_nfast) { w = fdiv(e, L, invL); k = e - w * L; }
-                else { w = e & (W - 1); k = e >> lw; }
-                cpx<R> c = cw[i];
-                if (osign > 0) c.y = -c.y;
-                if (w < m.wvalid)
-                    st(m.ob + k * m.osn + w * m.osw, k * m.bn + w * m.bw + m.b0, m.t0 + w * m.t1, buf[i] * c);
-            }
+        // transform 2 (opposite sign): from LDS, the last stage to global memory
+        Ns = 1;
+        for (int s = 0; s < nst; ++s) {
+            const int r = d.rad[s];
+            if (s == nst - 1)
+                fft_stage_r<R, MAXE, NBMAX, false, true>(r, lds, d, m, ld, st, tw, twf, Ns, -d.sign, tid, T);
+            else
+                fft_stage_r<R, MAXE, NBMAX, false, false>(r, lds, d, m, ld, st, tw, twf, Ns, -d.sign, tid, T);
+            Ns *= r;
         }
     }
 }
 
-template <typename R, typename LD>
-hipError_t launch_pass(const PassDesc& d, const LD& ld, const StorePlain<R>& st, const cpx<R>* tw,
-                       const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+template <typename R, int MAXE, int NBMAX, int MAXT>
+static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                                 const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
     static bool attr_set = false;
+    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT>;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_pass_kernel<R, LD>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);
+    const size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);
     const int ga = d.xcd_rows ? kXcds * ((d.tiles_a + kXcds - 1) / kXcds) : d.tiles_a;
     dim3 grid(d.tiles_b, ga), block(d.nthreads);
-    hipLaunchKernelGGL((fft_pass_kernel<R, LD>), grid, block, shm, s, d, ld, st, tw, twf, chainvec, chainscale);
+    hipLaunchKernelGGL(kern, grid, block, shm, s, d, ld, st, tw, twf, chainvec, chainscale);
     return hipGetLastError();
 }
 
-template hipError_t launch_pass<float, LoadPlain<float>>(const PassDesc&, const LoadPlain<float>&,
+template <typename R>
+hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                       const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+    if (d.one_bfly)
+        return launch_variant<R, OneBflyElems<R>::value, 1, OneBflyThreads<R>::value>(d, ld, st, tw, twf, chainvec, chainscale, s);
+    return launch_variant<R, MaxElems<R>::value, 64, 1024>(d, ld, st, tw, twf, chainvec, chainscale, s);
+}
+
+template hipError_t launch_pass<float>(const PassDesc&, const LoadPlain<float>&,
                                                          const StorePlain<float>&, const cpx<float>*,
                                                          const cpx<float>*, const cpx<float>*, float, hipStream_t);
-template hipError_t launch_pass<double, LoadPlain<double>>(const PassDesc&, const LoadPlain<double>&,
+template hipError_t launch_pass<double>(const PassDesc&, const LoadPlain<double>&,
                                                            const StorePlain<double>&, const cpx<double>*,
                                                            const cpx<double>*, const cpx<double>*, double,
                                                            hipStream_t);
-template hipError_t launch_pass<float, LoadGather<float>>(const PassDesc&, const LoadGather<float>&,
-                                                          const StorePlain<float>&, const cpx<float>*,
-                                                          const cpx<float>*, const cpx<float>*, float,
-                                                          hipStream_t);
-template hipError_t launch_pass<double, LoadGather<double>>(const PassDesc&, const LoadGather<double>&,
-                                                            const StorePlain<double>&, const cpx<double>*,
-                                                            const cpx<double>*, const cpx<double>*, double,
-                                                            hipStream_t);
-
-bool factor_radices(int L, int* nst, int* rad) {
-    int n = 0, m = L;
-    const int order[6] = {16, 8, 4, 2, 5, 3};
-    for (int r : order) {
-        while (m % r == 0) {
-            if (n >= kMaxStages) return false;
-            rad[n++] = r;
-            m /= r;
+// Radix sequence of a 5-smooth length with the fewest stages (then the largest leading radices)
+// from the radices the kernel implements; radices above max_radix are not used.
+bool factor_radices(int L, int* nst, int* rad, int max_radix) {
+    static const int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+    // best[n] = fewest stages for length n (n <= L), by dynamic programming over divisors
+    std::vector<int> best(L + 1, 1 << 20), pick(L + 1, 0);
+    best[1] = 0;
+    for (int n = 2; n <= L; ++n) {
+        if (L % n) continue;
+        for (int r : kRadices) {
+            if (r > max_radix || n % r) continue;
+            if (best[n / r] + 1 < best[n]) {
+                best[n] = best[n / r] + 1;
+                pick[n] = r;
+            }
         }
     }
-    *nst = n;
-    return m == 1;
+    if (best[L] >= (1 << 20) || best[L] > kMaxStages) return false;
+    int n = L, k = 0;
+    while (n > 1) {
+        rad[k++] = pick[n];
+        n /= pick[n];
+    }
+    *nst = k;
+    return true;
+}
+
+// The per-lane byte offsets of a pass's first-stage loads and last-stage stores (element j + t L/r of
+// lane (j, w) sits at the uniform base of row t plus the lane offset) must fit in 32 bits.
+bool pass_offsets_fit(const PassDesc& d, int esize) {
+    const TileMap m = tile_map(d, 0, 0);
+    const int64_t W = d.W;
+    const int64_t lin = (int64_t)(d.L / d.rad[0] - 1) * m.isn + (W - 1) * m.isw;
+    const int64_t lout = (int64_t)(d.L / d.rad[d.nst - 1] - 1) * m.osn + (W - 1) * m.osw;
+    const int64_t lim = (int64_t)1 << 32;
+    return lin >= 0 && lout >= 0 && lin * esize < lim && lout * esize < lim;
+}
+
+// Threads for one butterfly per thread per stage: the largest stage's butterfly count, rounded up to
+// whole waves; -1 if that exceeds max_threads.
+int pick_threads_one(int L, int W, int nst, const int* rad, int max_threads) {
+    int need = 0;
+    for (int s = 0; s < nst; ++s) need = std::max(need, (L / rad[s]) * W);
+    const int T = (need + 63) / 64 * 64;
+    return T <= max_threads ? T : -1;
 }
 
 int pick_threads(int L, int W, int nst, const int* rad, int max_elems) {
@@ -500,7 +731,7 @@ int pick_threads(int L, int W, int nst, const int* rad, int max_elems) {
             int r = rad[s];
             int B = (L / r) * W;
             int per = (B + T - 1) / T;
-            if (per > max_elems / r) ok = false;
+            if (per > std::min(max_elems / r, kMaxBfly)) ok = false;
         }
         if (ok) return T;
     }
