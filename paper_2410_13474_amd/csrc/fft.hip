@@ -430,11 +430,11 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     // butterfly's addresses out of the stage loop (they would stay live across all stages)
     int tid_s = tid;
     asm volatile("" : "+v"(tid_s));
-    // the same for the tile origins, which would otherwise pin every stage's global bases in
-    // scalar registers for the whole kernel
-    int ib_s = m.ib, ob_s = m.ob;
-    asm volatile("" : "+s"(ib_s), "+s"(ob_s));
-    const int L = d.L, lw = d.logW, W = 1 << lw;
+    // the same for the tile origins and the length, which would otherwise pin every stage's
+    // global bases and loop bounds in scalar registers for the whole kernel
+    int ib_s = m.ib, ob_s = m.ob, L = d.L;
+    asm volatile("" : "+s"(ib_s), "+s"(ob_s), "+s"(L));
+    const int lw = d.logW, W = 1 << lw;
     const int LR = L / RAD;
     const int B = LR << lw;
     const int tstride = L / (Ns * RAD);
