@@ -205,6 +205,7 @@ struct nufds_plan {
     bool has_run = false;
     void* result = nullptr;  // buffer holding F after the last execute
     int tile_cap = 0;        // LDS tile capacity override captured at creation (0: none)
+    int col_w = 0;           // column-tile width override captured at creation (0: default)
     // per-launch timing
     int timing_cap = 0;                        // executes to record (0: timing off)
     int timed_execs = 0;                       // executes recorded so far
@@ -310,7 +311,9 @@ static void chirp_vector(int M, int N, double pitch, double wavelength, double z
 struct Limits {
     size_t esize;    // bytes per complex element
     int tile_elems;  // LDS tile capacity, elements
-    int col_w;       // columns per tile (128-byte runs)
+    int row_w;       // transforms per tile of the four-step row passes
+    int col_w;       // columns per tile of the plain column passes (256-byte runs)
+    int chain_w;     // columns per tile of the fused column chain pass
     int max_elems;   // register budget per thread and stage
 };
 
@@ -321,13 +324,22 @@ static int tile_override() {
     return e ? std::atoi(e) : 0;
 }
 
-static Limits limits_for(size_t esize, int cap) {
+// NUFDS_COL_W sets the columns per tile of the column passes (a power of two, 1-64), for tuning.
+static int col_w_override() {
+    const char* e = std::getenv("NUFDS_COL_W");
+    const int w = e ? std::atoi(e) : 0;
+    return (w >= 1 && w <= 64 && (w & (w - 1)) == 0) ? w : 0;
+}
+
+static Limits limits_for(size_t esize, int cap, int colw) {
     Limits l;
     l.esize = esize;
     // logical elements whose padded LDS footprint (one pad per 32) fits in 160 KB
     l.tile_elems = (int)(((160 * 1024) / esize - 1) * 32 / 33);
     if (cap > 0) l.tile_elems = std::min(l.tile_elems, cap);
-    l.col_w = esize == 8 ? 16 : 8;
+    l.row_w = esize == 8 ? 16 : 8;
+    l.col_w = colw > 0 ? colw : (esize == 8 ? 32 : 16);
+    l.chain_w = esize == 8 ? 16 : 8;
     l.max_elems = esize == 8 ? 16 : 8;
     return l;
 }
@@ -406,10 +418,14 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
     } else {
         d.rows = L;
         d.cols = other;
-        if ((int64_t)L * lim.col_w <= lim.tile_elems) {
+        // widest column tile that holds the whole column (down to 64-byte runs)
+        int w = chain ? lim.chain_w : lim.col_w;
+        const int wmin = lim.esize == 8 ? 8 : 4;
+        while (w > wmin && (int64_t)L * w > lim.tile_elems) w /= 2;
+        if ((int64_t)L * w <= lim.tile_elems) {
             d.kind = K_COL1;
             d.L = L;
-            d.W = lim.col_w;
+            d.W = w;
             d.chain = chain;
             d.tiles_a = 1;
             d.tiles_b = (other + d.W - 1) / d.W;
@@ -422,15 +438,23 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
     }
     // four-step: A (over n1) then B (over n2); a chain fuses the first B and the second A
     int L1, L2;
-    const int W = lim.col_w;
-    if (!four_step_split(L, W, lim, &L1, &L2)) return false;
+    int Wp = axis == 0 ? lim.row_w : lim.col_w;       // plain passes
+    int Wc = axis == 0 ? lim.row_w : lim.chain_w;     // fused chain pass
+    // narrower tiles when no split fits the wide ones (small LDS capacities)
+    const int wmin = lim.esize == 8 ? 8 : 4;
+    while (!four_step_split(L, std::max(Wp, Wc), lim, &L1, &L2)) {
+        if (std::max(Wp, Wc) <= wmin) return false;
+        Wp = std::max(wmin, Wp / 2);
+        Wc = std::max(wmin, Wc / 2);
+    }
     ap->single = false;
     PassDesc a = d, b = d;
     a.L1 = b.L1 = L1;
     a.L2 = b.L2 = L2;
     a.Lf = b.Lf = L;
     a.chain = b.chain = 0;
-    a.W = b.W = W;
+    a.W = Wp;
+    b.W = chain ? Wc : Wp;
     a.L = L1;
     b.L = L2;
     if (axis == 0) {
@@ -439,14 +463,14 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
         a.tiles_b = (L2 + a.W - 1) / a.W;
         b.kind = chain ? K_ROWBA : K_ROWB;
         b.tiles_a = other;
-        b.tiles_b = (L1 + W - 1) / W;
+        b.tiles_b = (L1 + b.W - 1) / b.W;
     } else {
         a.kind = K_COLA;
         a.tiles_a = L2;
-        a.tiles_b = (other + W - 1) / W;
+        a.tiles_b = (other + a.W - 1) / a.W;
         b.kind = chain ? K_COLBA : K_COLB;
         b.tiles_a = L1;
-        b.tiles_b = (other + W - 1) / W;
+        b.tiles_b = (other + b.W - 1) / b.W;
     }
     b.chain = chain;
     if (!finish_desc(a, lim) || !finish_desc(b, lim)) return false;
@@ -459,17 +483,17 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
         c.L2 = L1;
         c.Lf = L;
         c.L = L1;
-        c.W = W;
+        c.W = Wp;
         c.chain = 0;
         c.sign = -sign;
         if (axis == 0) {
             c.kind = K_ROWB;
             c.tiles_a = other;
-            c.tiles_b = (L2 + W - 1) / W;
+            c.tiles_b = (L2 + Wp - 1) / Wp;
         } else {
             c.kind = K_COLB;
             c.tiles_a = L2;
-            c.tiles_b = (other + W - 1) / W;
+            c.tiles_b = (other + Wp - 1) / Wp;
         }
         if (!finish_desc(c, lim)) return false;
         ap->passes.push_back(c);
@@ -569,7 +593,7 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, void* out, hipStream_t s
 
 template <typename R>
 static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out, hipStream_t s) {
-    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap);
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     const nufds_plan_info_t& g = p->info;
     const int nx = g.nx, ny = g.ny, mx = g.mx, my = g.my;
     void* spec = p->spec.p;
@@ -662,7 +686,7 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
 
 template <typename R>
 static nufds_status_t prepare_impl(nufds_plan* p) {
-    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap);
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     const nufds_plan_info_t& g = p->info;
     // every transform must have a pass plan; create the twiddle tables its passes read, so that
     // execute only enqueues kernels
@@ -712,6 +736,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     p->prec = precision;
     p->esize = precision == NUFDS_C64 ? 8 : 16;
     p->tile_cap = tile_override();
+    p->col_w = col_w_override();
     auto bail = [&](nufds_status_t st) {
         std::string msg = nufds_last_error();
         plan_free(p);

@@ -85,46 +85,6 @@ struct LoadPlain {
     R scale;
 };
 
-// Keys cubic convolution weights (a = -1/2) of the taps at floor-1 .. floor+2 for fraction t.
-template <typename R>
-__device__ __forceinline__ void keys4(R t, R* w) {
-    R t2 = t * t, t3 = t2 * t;
-    w[0] = R(-0.5) * t3 + t2 - R(0.5) * t;
-    w[1] = R(1.5) * t3 - R(2.5) * t2 + R(1);
-    w[2] = R(-1.5) * t3 + R(2) * t2 + R(0.5) * t;
-    w[3] = R(0.5) * t3 - R(0.5) * t2;
-}
-
-// Keys 4 x 4 interpolation of the [ny][nx] spectrum at fractional sample (px, py), periodic.
-template <typename R>
-__device__ __forceinline__ cpx<R> keys_spectrum(const cpx<R>* __restrict__ spec, int nx, int ny, double px,
-                                                double py) {
-    const double fx = floor(px), fy = floor(py);
-    const int ix = (int)fx - 1, iy = (int)fy - 1;
-    R wx[4], wy[4];
-    keys4<R>(R(px - fx), wx);
-    keys4<R>(R(py - fy), wy);
-    int cols[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        int c = ix + a;
-        c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
-        cols[a] = c;
-    }
-    cpx<R> acc = mk(R(0), R(0));
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        int r = iy + b;
-        r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
-        const cpx<R>* row = spec + (int64_t)r * nx;
-        cpx<R> racc = mk(R(0), R(0));
-#pragma unroll
-        for (int a = 0; a < 4; ++a) racc = racc + row[cols[a]] * wx[a];
-        acc = acc + racc * wy[b];
-    }
-    return acc;
-}
-
 // ---------------------------------------------------------------- stores
 
 // Destination of a pass: out[offset] = v * scale * ((-1)^(index along the axis) if sign_axis).
@@ -132,6 +92,13 @@ template <typename R>
 struct StorePlain {
     cpx<R>* out;
     int sign_axis;
+    R scale;
+};
+
+// Element-wise factor between the two transforms of a chain pass: vec[n cn + w cw + c0] * scale.
+template <typename R>
+struct ChainMul {
+    const cpx<R>* vec;
     R scale;
 };
 

@@ -420,10 +420,11 @@ struct StageNb {
 // order that makes their global accesses contiguous (j fastest for transforms that run along memory,
 // w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
 // precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
-template <typename R, int RAD, int MAXE, int NBMAX, bool FIRST, bool LAST>
+template <typename R, int RAD, int MAXE, int NBMAX, bool FIRST, bool LAST, bool CHAIN>
 __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
-                                          const StorePlain<R>& st, const cpx<R>* __restrict__ tw,
-                                          const cpx<R>* __restrict__ twf, int Ns, int sign, int tid, int T) {
+                                          const StorePlain<R>& st, const ChainMul<R>& ch,
+                                          const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
+                                          int sign, int tid, int T) {
     constexpr int NB = StageNb<RAD, MAXE, NBMAX>::value;
     constexpr uint32_t ES = sizeof(cpx<R>);
     // per-stage opaque copy of the thread index: keeps the compiler from hoisting every
@@ -432,7 +433,8 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     asm volatile("" : "+v"(tid_s));
     // the same for the tile origins and the length, which would otherwise pin every stage's
     // global bases and loop bounds in scalar registers for the whole kernel
-    int ib_s = m.ib, ob_s = m.ob, L = d.L;
+    int ib_s = __builtin_amdgcn_readfirstlane(m.ib), ob_s = __builtin_amdgcn_readfirstlane(m.ob);
+    int L = __builtin_amdgcn_readfirstlane(d.L);
     asm volatile("" : "+s"(ib_s), "+s"(ob_s), "+s"(L));
     const int lw = d.logW, W = 1 << lw;
     const int LR = L / RAD;
@@ -444,6 +446,7 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     cpx<R> v[NB][RAD];
     cpx<R> cw[NB];
     cpx<R> c4a[NB], c4b[NB];
+    cpx<R> cv[CHAIN ? NB : 1][CHAIN ? RAD : 1];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int b0 = tid_s + i * T;
@@ -463,6 +466,16 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
         } else {
 #pragma unroll
             for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_pad(((j + t * LR) << lw) + w)];
+        }
+        if (CHAIN) {
+            // last stage of the first transform of a chain pass: outputs sit at natural positions
+            // pos = j + t LR; fetch the chain vector at pos cn + w cw + c0 now, so the loads overlap
+            // the barrier and the butterfly
+            // (the vector is short: one scalar base, 32-bit offsets)
+            const int c = j * m.cn + (w < m.wvalid ? w : 0) * m.cw + m.c0;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t)
+                cv[i][t] = load_at<R>(uniform_base(ch.vec), (uint32_t)(c + t * LR * m.cn) * ES);
         }
         if (LAST && m.twiddle) {
             // outputs sit at pos = j + t LR (Ns = LR in the last stage); the four-step twiddle
@@ -531,6 +544,10 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
                         tf = tf * step;
                     }
                 }
+            } else if (CHAIN) {
+#pragma unroll
+                for (int t = 0; t < RAD; ++t)
+                    lds[lds_pad(((j + t * LR) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)] * cv[i][t] * ch.scale;
             } else {
                 const int base = q * Ns * RAD + k;
 #pragma unroll
@@ -542,13 +559,14 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     if (!LAST) __syncthreads();
 }
 
-template <typename R, int MAXE, int NBMAX, bool FIRST, bool LAST>
-__device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
-                                            const StorePlain<R>& st, const cpx<R>* __restrict__ tw,
-                                            const cpx<R>* __restrict__ twf, int Ns, int sign, int tid, int T) {
+template <typename R, int MAXE, int NBMAX, bool FIRST, bool LAST, bool CHAIN>
+__device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m,
+                                            const LoadPlain<R>& ld, const StorePlain<R>& st, const ChainMul<R>& ch,
+                                            const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
+                                            int sign, int tid, int T) {
 #define NUFDS_STAGE(RR)                                                                             \
     if constexpr ((RR) <= MAXE)                                                                     \
-        fft_stage<R, RR, MAXE, NBMAX, FIRST, LAST>(lds, d, m, ld, st, tw, twf, Ns, sign, tid, T)
+        fft_stage<R, RR, MAXE, NBMAX, FIRST, LAST, CHAIN>(lds, d, m, ld, st, ch, tw, twf, Ns, sign, tid, T)
     switch (r) {
         case 16: NUFDS_STAGE(16); break;
         case 8: NUFDS_STAGE(8); break;
@@ -575,8 +593,6 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x, T = blockDim.x;
-    const int L = d.L, lw = d.logW, W = 1 << lw;
-    const int E = L << lw;
     int ta = blockIdx.y, tb = blockIdx.x;
     if (d.xcd_rows) {
         // workgroups are dispatched round-robin over the XCDs: give each XCD a contiguous range of
@@ -596,51 +612,45 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     const TileMap m = tile_map(d, ta, tb);
     const int nst = d.nst;
 
-    // transform 1: stage 0 reads global memory; the last stage writes global memory unless a
-    // second transform follows in this pass
+    const ChainMul<R> ch{chainvec, chainscale};
+
+    // transform 1: stage 0 reads global memory; the last stage writes global memory, or, in a chain
+    // pass, multiplies by the chain vector (the chirp of Eq. 2) on its way to LDS
     int Ns = 1;
-    const bool one = !d.chain;
-    for (int s = 0; s < nst; ++s) {
-        const int r = d.rad[s];
-        const bool first = s == 0, last = one && s == nst - 1;
-        if (first && last) fft_stage_r<R, MAXE, NBMAX, true, true>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
-        else if (first) fft_stage_r<R, MAXE, NBMAX, true, false>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
-        else if (last) fft_stage_r<R, MAXE, NBMAX, false, true>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
-        else fft_stage_r<R, MAXE, NBMAX, false, false>(r, lds, d, m, ld, st, tw, twf, Ns, d.sign, tid, T);
-        Ns *= r;
-    }
-    if (d.chain) {
-        // element-wise multiply by the chain vector (the chirp of Eq. 2), vector loads batched
-        constexpr int GC = MaxElems<R>::value / 2;
-        for (int r0 = 0; r0 < E; r0 += GC * T) {
-            cpx<R> cv[GC];
-#pragma unroll
-            for (int i = 0; i < GC; ++i) {
-                const int e0 = r0 + tid + i * T;
-                const int e = e0 < E ? e0 : 0;
-                const int w = e & (W - 1), n = e >> lw;
-                cv[i] = chainvec[n * m.cn + w * m.cw + m.c0];
-            }
-#pragma unroll
-            for (int i = 0; i < GC; ++i) {
-                const int e = r0 + tid + i * T;
-                if (e < E) {
-                    const int p = lds_pad(e);
-                    lds[p] = lds[p] * cv[i] * chainscale;
-                }
-            }
-        }
-        __syncthreads();
-        // transform 2 (opposite sign): from LDS, the last stage to global memory
-        Ns = 1;
+    const int sg = d.sign;
+#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, F, L, C>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg, tid, T)
+    if (!d.chain) {
         for (int s = 0; s < nst; ++s) {
             const int r = d.rad[s];
-            if (s == nst - 1)
-                fft_stage_r<R, MAXE, NBMAX, false, true>(r, lds, d, m, ld, st, tw, twf, Ns, -d.sign, tid, T);
-            else
-                fft_stage_r<R, MAXE, NBMAX, false, false>(r, lds, d, m, ld, st, tw, twf, Ns, -d.sign, tid, T);
+            const bool first = s == 0, last = s == nst - 1;
+            if (first && last) NUFDS_RUN(true, true, false);
+            else if (first) NUFDS_RUN(true, false, false);
+            else if (last) NUFDS_RUN(false, true, false);
+            else NUFDS_RUN(false, false, false);
             Ns *= r;
         }
+        return;
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int r = d.rad[s];
+        const bool first = s == 0, last = s == nst - 1;
+        if (first && last) NUFDS_RUN(true, false, true);
+        else if (first) NUFDS_RUN(true, false, false);
+        else if (last) NUFDS_RUN(false, false, true);
+        else NUFDS_RUN(false, false, false);
+        Ns *= r;
+    }
+#undef NUFDS_RUN
+    // transform 2 (opposite sign): from LDS, the last stage to global memory
+    const int sg2 = -d.sign;
+    Ns = 1;
+    for (int s = 0; s < nst; ++s) {
+        const int r = d.rad[s];
+        if (s == nst - 1)
+            fft_stage_r<R, MAXE, NBMAX, false, true, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+        else
+            fft_stage_r<R, MAXE, NBMAX, false, false, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+        Ns *= r;
     }
 }
 
