@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (a reference for hardware byte counters)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the partial-view latency run")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     return ap.parse_args()
 
 
@@ -119,6 +121,108 @@ def cpu_baseline(torch, N):
     return rec, errs
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo = int(math.floor(k))
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def serving(torch, N, n_requests):
+    """Partial views of one cached 8192^2 120 deg hologram (2048 points, z ~ U[5, 15] mm): square
+    views of side S ~ U{512, 1024, 2048, 4096} at pitch Delta_F, centres uniform over the image,
+    reconstruction distance z ~ U[5, 15] mm, seed 2004.  First the closed-loop capacity (8 requests
+    outstanding), then Poisson arrivals at 70% of it; latency runs from submit to the completion of
+    the request's last kernel."""
+    import numpy as np
+    import synth
+
+    n, fov = 8192, 120.0
+    dp = synth.fov_pitch(LAM, fov)
+    pc = synth.draw_points(2004, 2048, n, n, dp, LAM, 5e-3, 15e-3)
+    H = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    N.synth_hologram(pc.as_array(), n, n, dp, LAM, H)
+    H = H.to(torch.complex64)
+    torch.cuda.synchronize()
+    spec = N.Spectrum(H, LAM, dp)
+    del H
+    rng = np.random.default_rng(2004)
+    reqs = []
+    max_m = 0
+    for _ in range(n_requests):
+        z = float(rng.uniform(5e-3, 15e-3))
+        S = int(rng.choice([512, 1024, 2048, 4096]))
+        g = N.plan_geometry(LAM, dp, n, n, z)
+        half = g["image_size"] / 2 - S * g["dfx"] / 2
+        v = dict(center_x=float(rng.uniform(-half, half)), center_y=float(rng.uniform(-half, half)),
+                 pitch_x=0.0, pitch_y=0.0, nx=S, ny=S)
+        gv = N.plan_geometry(LAM, dp, n, n, z, view=v)
+        max_m = max(max_m, gv["mx"], gv["my"])
+        reqs.append((z, v))
+    srv = N.Server("c64", max_frt_size=max_m, max_view_size=4096, max_inflight=4)
+    ring = 32
+    outs = [torch.empty((4096, 4096), dtype=torch.complex64, device="cuda") for _ in range(ring)]
+    pending = [None] * ring
+
+    def run(order, arrivals=None):
+        lat = []
+        t_start = time.perf_counter()
+        for i, (z, v) in enumerate(order):
+            slot = i % ring
+            if pending[slot] is not None:
+                lat.append(srv.wait(pending[slot]))
+            if arrivals is not None:
+                while time.perf_counter() - t_start < arrivals[i]:
+                    pass
+            S = v["nx"]
+            o = outs[slot].view(-1)[: S * S].view(S, S)
+            pending[slot] = srv.submit(spec, z, o, view=v)
+        for slot in range(ring):
+            if pending[slot] is not None:
+                lat.append(srv.wait(pending[slot]))
+                pending[slot] = None
+        return lat, time.perf_counter() - t_start
+
+    log(f"serving: {n_requests} requests, FrT sizes up to {max_m}; warm-up pass")
+    run(reqs[: min(len(reqs), 400)])
+    # closed loop: at most 8 requests outstanding (the ring is deeper, so cap by waiting)
+    lat_c, t_closed = [], time.perf_counter()
+    window = []
+    for i, (z, v) in enumerate(reqs):
+        if len(window) == 8:
+            lat_c.append(srv.wait(window.pop(0)[0]))
+        slot = i % ring
+        S = v["nx"]
+        o = outs[slot].view(-1)[: S * S].view(S, S)
+        window.append((srv.submit(spec, z, o, view=v), slot))
+    for t, _ in window:
+        lat_c.append(srv.wait(t))
+    t_closed = time.perf_counter() - t_closed
+    capacity = len(reqs) / t_closed
+    pix = sum(v["nx"] * v["ny"] for _, v in reqs)
+    log(f"serving closed loop: {capacity:.1f} req/s, {pix / t_closed / 1e6:.0f} Mpix/s")
+    rate = 0.7 * capacity
+    gaps = np.random.default_rng(20040).exponential(1.0 / rate, size=len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    lat_o, t_open = run(reqs, arrivals)
+    p50, p99 = percentile(lat_o, 0.50), percentile(lat_o, 0.99)
+    log(f"serving open loop at 70%: p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+    srv.close()
+    spec.close()
+    del outs
+    torch.cuda.empty_cache()
+    return {"p50": p50, "p99": p99, "requests": len(reqs), "load": 0.7, "rate_per_s": rate,
+            "capacity_per_s": capacity, "closed_loop_mpix_s": pix / t_closed / 1e6,
+            "closed_loop_p50": percentile(lat_c, 0.5), "closed_loop_p99": percentile(lat_c, 0.99),
+            "max_frt_size": max_m, "inflight": 4,
+            "workload": "8192^2 120 deg hologram (2048 points), spectrum cached; square views S in "
+                        "{512,1024,2048,4096} at Delta_F, uniform centres, z ~ U[5,15] mm, seed 2004; "
+                        "Poisson arrivals at 70% of closed-loop capacity"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -188,6 +292,10 @@ def main():
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
 
+    serve = None
+    if not args.no_serving:
+        serve = serving(torch, N, args.serving_requests)
+
     cpu = None
     errs = {}
     if not args.no_cpu:
@@ -217,7 +325,7 @@ def main():
         "kernels": {p: {k: {"avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),
                             "per_step": v["launches_per_step"]} for k, v in r["kernels"].items()}
                     for p, r in results.items()},
-        "partial_view_latency_ms": None,
+        "partial_view_latency_ms": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -215,6 +215,114 @@ nufds_status_t nufds_synth_hologram(const double* h_points, int32_t n_points, in
                                     int32_t ny, double pitch, double wavelength,
                                     nufds_precision_t precision, void* d_out, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * A hologram is often reconstructed many times: partial views of chosen
+ * position and size (Sec. 4, partial view) at several depths.  The forward
+ * FFT of step 2 depends only on the hologram, and the stretch map of step 1
+ * (Eqs. 9-10 with Eq. 16) only on the hologram's size, pitch and wavelength,
+ * so both are computed once and every request runs steps 2b-5 on the
+ * sub-band its view needs.
+ */
+
+typedef struct nufds_spectrum* nufds_spectrum_t;
+
+/*
+ * nufds_spectrum_create -- the centred forward FFT of one hologram (Sec. 4,
+ * step 2, before the stretch), kept in device memory for any number of
+ * reconstructions.
+ *
+ * wavelength, pitch, nx, ny, precision: as for nufds_plan_create.
+ * flags: only NUFDS_FLAG_CONVERGING may be set (diverging input is
+ * conjugated here).  d_hologram: device [ny][nx] of the precision, read
+ * during the call.  The transform is enqueued on stream and the call waits
+ * for it, so the hologram may be freed on return.  The spectrum owns
+ * nx * ny complex elements of device memory until nufds_spectrum_destroy.
+ * Errors: INVALID_ARG (ranges, NULLs, other flag bits), UNSUPPORTED (sizes
+ * beyond the kernels), OUT_OF_MEMORY, HIP.  On error *spectrum is NULL.
+ */
+nufds_status_t nufds_spectrum_create(nufds_spectrum_t* spectrum, double wavelength, double pitch,
+                                     int32_t nx, int32_t ny, nufds_precision_t precision,
+                                     uint32_t flags, const void* d_hologram, void* stream);
+
+/* nufds_spectrum_destroy -- wait for the device and free the spectrum.  NULL is a no-op.  No
+ * queued or running execute or server request may still read it. */
+nufds_status_t nufds_spectrum_destroy(nufds_spectrum_t spectrum);
+
+/*
+ * nufds_execute_spectrum -- nufds_execute from a cached spectrum: the stretch,
+ * inverse FFT, Fresnel transform and output remap (steps 2-5 after the
+ * forward FFT).  The plan and the spectrum must agree on nx, ny, wavelength,
+ * pitch, precision and NUFDS_FLAG_CONVERGING, else INVALID_ARG.  Otherwise
+ * as nufds_execute (asynchronous on stream, one execute in flight per plan);
+ * the output is bit-identical to nufds_execute of the same hologram.
+ */
+nufds_status_t nufds_execute_spectrum(nufds_plan_t plan, nufds_spectrum_t spectrum, void* d_out,
+                                      void* stream);
+
+typedef struct nufds_server* nufds_server_t;
+
+typedef struct {
+    int32_t precision;            /* nufds_precision_t of every spectrum served */
+    int32_t max_frt_size;         /* largest FrT size M (either axis) of a request, even, > 0 */
+    int32_t max_view_size;        /* largest output side of a request, samples, > 0 */
+    int32_t max_inflight;         /* requests executing at once (one stream each), >= 1 */
+    uint64_t max_workspace_bytes; /* device bytes of all workspaces together; 0 = no limit */
+} nufds_server_options_t;
+
+/*
+ * nufds_server_create -- a server of views of cached spectra.
+ *
+ * The server owns `slots` workspaces, each two max_frt_size^2 complex
+ * buffers plus the request's chirp and output-map vectors and one HIP
+ * stream (default priority): slots = max_inflight, lowered until
+ * slots * workspace <= max_workspace_bytes (admission by memory).  A
+ * dispatcher thread starts queued requests in arrival order as soon as a
+ * slot is free (continuous batching: a request starts when any earlier one
+ * ends, not when a batch fills) and a completion thread records each
+ * request's latency.  The stretch-map table of each hologram geometry is
+ * built on first use and shared by all requests of that geometry.  Uses the
+ * current device.  Errors: INVALID_ARG (NULLs, ranges), OUT_OF_MEMORY (not
+ * one workspace fits), HIP.  On error *server is NULL.
+ */
+nufds_status_t nufds_server_create(nufds_server_t* server, const nufds_server_options_t* opt);
+
+/*
+ * nufds_server_submit -- queue one view of a spectrum at distance z (metres).
+ *
+ * view as for nufds_plan_create (NULL: full view).  flags: NUFDS_FLAG_NO_STRETCH
+ * and NUFDS_FLAG_NO_REMAP apply per request; NUFDS_FLAG_CONVERGING is the
+ * spectrum's.  d_out: device [view.ny][view.nx] complex of the server's
+ * precision, written by the request; it must stay valid until the request
+ * ends.  The request's geometry is checked before it is queued.  *ticket
+ * receives its id.  Thread-safe.  Errors: INVALID_ARG (NULLs, ranges,
+ * precision mismatch), UNSUPPORTED (FrT size or view beyond the server's
+ * limits or the kernels'), or the error a stopped server reports.
+ */
+nufds_status_t nufds_server_submit(nufds_server_t server, nufds_spectrum_t spectrum, double z,
+                                   const nufds_view_t* view, uint32_t flags, void* d_out,
+                                   uint64_t* ticket);
+
+/*
+ * nufds_server_poll -- state of a request without consuming it: *state is
+ * 0 (queued or running), 1 (done) or 2 (failed); once done, *latency_ms is
+ * the host time from submit to the completion of its last kernel.
+ * Errors: INVALID_ARG (NULLs, unknown ticket).
+ */
+nufds_status_t nufds_server_poll(nufds_server_t server, uint64_t ticket, int32_t* state,
+                                 double* latency_ms);
+
+/*
+ * nufds_server_wait -- block until the request ends, write its latency
+ * (latency_ms may be NULL), release the ticket and return the request's
+ * status (its message through nufds_last_error on the calling thread).
+ * Errors: INVALID_ARG (NULL server, unknown ticket), or the request's own.
+ */
+nufds_status_t nufds_server_wait(nufds_server_t server, uint64_t ticket, double* latency_ms);
+
+/* nufds_server_destroy -- run every queued request to its end, stop the threads and free the
+ * workspaces and tables.  NULL is a no-op. */
+nufds_status_t nufds_server_destroy(nufds_server_t server);
+
 /* nufds_status_string -- static text of a status code. */
 const char* nufds_status_string(nufds_status_t status);
 

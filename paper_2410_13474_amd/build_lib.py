@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnufds.so")
-SOURCES = ["api.cpp", "fft.hip", "kernels.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "fft.hip", "kernels.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -14,15 +14,10 @@
 #include "fft.h"
 #include "kernels.h"
 #include "nufds.h"
+#include "plan.h"
 #include "special.h"
 
 namespace nufds {
-
-#define NUFDS_TRY(x)                        \
-    do {                                    \
-        nufds_status_t st_ = (x);           \
-        if (st_ != NUFDS_OK) return st_;    \
-    } while (0)
 
 static thread_local std::string g_last_error;
 
@@ -40,7 +35,7 @@ nufds_status_t hip_fail(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------------ geometry
 
-static bool smooth5(int n) {
+bool smooth5(int n) {
     if (n <= 0) return false;
     for (int p : {2, 3, 5})
         while (n % p == 0) n /= p;
@@ -169,11 +164,9 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
 
 // ------------------------------------------------------------------ plan
 
-constexpr int kMaxLen = 65536;
-
 // Largest T(1) of the map over the band square |u|, |v| <= s of the unit disk: at u = s and the
 // largest admissible |v| (T_1 grows with both |u| and |v|).
-static double stretch_extent(double s) {
+double stretch_extent(double s) {
     const double v = std::min(s, std::sqrt((1.0 - s) * (1.0 + s)));
     const double av = std::sqrt((1.0 - v) * (1.0 + v));
     const double sig = std::min(1.0, s / av);
@@ -181,43 +174,28 @@ static double stretch_extent(double s) {
     return std::sqrt(av) * integral_i(sig, c);
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
+// Quadrant table extent |k_g| <= floor(T_max N D / lambda) + 2 per axis: every stretched frequency
+// with a pre-image in the hologram band.
+void table_extent(double wavelength, double pitch, int nx, int ny, int* kxt, int* kyt) {
+    const double ext = stretch_extent(wavelength / (2.0 * pitch));
+    *kxt = (int)std::floor(ext * nx * pitch / wavelength) + 2;
+    *kyt = (int)std::floor(ext * ny * pitch / wavelength) + 2;
+}
 
-}  // namespace nufds
+nufds_status_t check_sizes(const nufds_plan_info_t& g) {
+    if (g.mx > kMaxLen || g.my > kMaxLen || g.nx > kMaxLen || g.ny > kMaxLen || !smooth5(g.nx) || !smooth5(g.ny))
+        return fail(NUFDS_ERR_UNSUPPORTED, "sizes must be 5-smooth and at most 65536");
+    const int64_t kMaxArray = (int64_t)1 << 31;  // the FFT passes index elements with 32-bit integers
+    if ((int64_t)g.nx * g.ny >= kMaxArray || (int64_t)g.mx * g.my >= kMaxArray || (int64_t)g.sx * g.sy >= kMaxArray)
+        return fail(NUFDS_ERR_UNSUPPORTED, "hologram, FrT and output arrays must hold fewer than 2^31 elements");
+    return NUFDS_OK;
+}
 
-using namespace nufds;
+TwiddleCache::~TwiddleCache() {
+    for (auto& kv : tables) (void)hipFree(kv.second);
+}
 
-struct nufds_plan {
-    nufds_plan_info_t info{};
-    double wavelength = 0, pitch = 0, z = 0;
-    uint32_t flags = 0;
-    int prec = 0;
-    int device = 0;
-    size_t esize = 8;
-    DevBuf spec, work1, work2, table, chirp_x, chirp_y, ax, by;
-    int kxt = -1, kyt = -1;
-    std::map<int, void*> twiddles;
-    hipEvent_t done = nullptr;
-    hipStream_t last_stream = nullptr;
-    bool has_run = false;
-    void* result = nullptr;  // buffer holding F after the last execute
-    int tile_cap = 0;        // LDS tile capacity override captured at creation (0: none)
-    int col_w = 0;           // column-tile width override captured at creation (0: default)
-    // per-launch timing
-    int timing_cap = 0;                        // executes to record (0: timing off)
-    int timed_execs = 0;                       // executes recorded so far
-    bool recording = false;                    // the current execute is being recorded
-    std::vector<hipEvent_t> ev;                // pairs (start, end) per recorded launch
-    std::vector<nufds_kernel_time_t> launches; // names and bytes of the recorded launches
-    int nlaunch = 0;
-};
-
-namespace nufds {
-
-static nufds_status_t dev_alloc(DevBuf& b, size_t bytes) {
+nufds_status_t dev_alloc(DevBuf& b, size_t bytes) {
     b.bytes = bytes;
     if (bytes == 0) return NUFDS_OK;
     hipError_t e = hipMalloc(&b.p, bytes);
@@ -229,8 +207,8 @@ static nufds_status_t dev_alloc(DevBuf& b, size_t bytes) {
     return NUFDS_OK;
 }
 
-static void dev_free(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+void dev_free(DevBuf& b) {
+    if (b.p && b.owned) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
 }
@@ -246,8 +224,7 @@ static void plan_free(nufds_plan* p) {
     dev_free(p->chirp_y);
     dev_free(p->ax);
     dev_free(p->by);
-    for (auto& kv : p->twiddles) (void)hipFree(kv.second);
-    p->twiddles.clear();
+    p->twiddles.reset();
     if (p->done) (void)hipEventDestroy(p->done);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     delete p;
@@ -263,17 +240,17 @@ static nufds_status_t upload_complex(DevBuf& b, const std::vector<double>& re, c
     return NUFDS_OK;
 }
 
-// exp(-2 pi i m / L), m = 0 .. L-1, in float64 then rounded.
+// exp(-2 pi i m / L), m = 0 .. L-1, in float64 then rounded; created once per length and cache.
 template <typename R>
 static nufds_status_t twiddle_table(nufds_plan* p, int L, const cpx<R>** out) {
-    auto it = p->twiddles.find(L);
-    if (it != p->twiddles.end()) {
+    auto& tabs = p->twiddles->tables;
+    auto it = tabs.find(L);
+    if (it != tabs.end()) {
         *out = static_cast<const cpx<R>*>(it->second);
         return NUFDS_OK;
     }
     std::vector<cpx<R>> h(L);
     for (int m = 0; m < L; ++m) {
-        // angle reduced to the first octant-friendly form: use (m / L) in [0, 1)
         const double a = -2.0 * M_PI * (double)m / (double)L;
         h[m] = mk(R(std::cos(a)), R(std::sin(a)));
     }
@@ -285,14 +262,14 @@ static nufds_status_t twiddle_table(nufds_plan* p, int L, const cpx<R>** out) {
         (void)hipFree(d);
         return hip_fail(e, "hipMemcpy(twiddles)");
     }
-    p->twiddles[L] = d;
+    tabs[L] = d;
     *out = static_cast<const cpx<R>*>(d);
     return NUFDS_OK;
 }
 
 // The chirp exp(+i k xi^2 / 2z) of Eq. 2 at xi = (n - M/2) N D / M, phase in float64 reduced mod 2 pi.
-static void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::vector<double>& re,
-                         std::vector<double>& im) {
+void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::vector<double>& re,
+                  std::vector<double>& im) {
     re.resize(M);
     im.resize(M);
     const double cycles_per_m2 = 1.0 / (2.0 * wavelength * z);  // k xi^2 / 2z = 2 pi xi^2 / (2 lambda z)
@@ -319,13 +296,13 @@ struct Limits {
 
 // NUFDS_MAX_TILE_ELEMS lowers the LDS tile capacity (tests use it to drive the four-step passes
 // at small sizes); a plan reads it once, when it is created.
-static int tile_override() {
+int tile_override() {
     const char* e = std::getenv("NUFDS_MAX_TILE_ELEMS");
     return e ? std::atoi(e) : 0;
 }
 
 // NUFDS_COL_W sets the columns per tile of the column passes (a power of two, 1-64), for tuning.
-static int col_w_override() {
+int col_w_override() {
     const char* e = std::getenv("NUFDS_COL_W");
     const int w = e ? std::atoi(e) : 0;
     return (w >= 1 && w <= 64 && (w & (w - 1)) == 0) ? w : 0;
@@ -562,10 +539,10 @@ static void abs_range(int g0, int g1, int* lo, int* hi) {
 }
 
 template <typename R>
-static nufds_status_t run_stretch_gather(nufds_plan* p, void* out, hipStream_t s) {
+static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* out, hipStream_t s) {
     const nufds_plan_info_t& g = p->info;
     GatherArgs<R> a;
-    a.spec = static_cast<const cpx<R>*>(p->spec.p);
+    a.spec = static_cast<const cpx<R>*>(spec);
     a.out = static_cast<cpx<R>*>(out);
     a.table = static_cast<const double*>(p->table.p);
     a.kxt = p->kxt;
@@ -592,13 +569,9 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, void* out, hipStream_t s
 }
 
 template <typename R>
-static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out, hipStream_t s) {
+nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
-    const nufds_plan_info_t& g = p->info;
-    const int nx = g.nx, ny = g.ny, mx = g.mx, my = g.my;
-    void* spec = p->spec.p;
-    void* w1 = p->work1.p;
-    void* w2 = p->work2.p;
+    const int nx = p->info.nx, ny = p->info.ny;
     const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
     AxisPlan ap;
 
@@ -619,6 +592,18 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
         NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, R(1), s));
         NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, R(1), s));
     }
+    return NUFDS_OK;
+}
+
+template <typename R>
+nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_t s) {
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
+    const nufds_plan_info_t& g = p->info;
+    const int mx = g.mx, my = g.my;
+    void* w1 = p->work1.p;
+    void* w2 = p->work2.p;
+    const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
+    AxisPlan ap;
 
     // steps 2b-3 along x: stretch-gather, centred IDFT, chirp / M_x, centred DFT (signs cancel to
     // (-1)^k' on input and (-1)^m on output)
@@ -627,7 +612,7 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
     if (!build_axis(0, mx, my, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT row length");
     void* res;
     // the stretch-gather runs as a kernel of its own (2-D tiles, each quadrant table entry read once)
-    NUFDS_TRY(run_stretch_gather<R>(p, w2, s));
+    NUFDS_TRY(run_stretch_gather<R>(p, spec, w2, s));
     if (ap.single) {
         NUFDS_TRY(run_pass<R>(p, "xop", ap.passes[0], w2, w1, 0, 0, 1, R(1), cxv, R(1) / R(mx), s));
         res = w1;
@@ -685,14 +670,15 @@ static nufds_status_t execute_impl(nufds_plan* p, const void* d_in, void* d_out,
 }
 
 template <typename R>
-static nufds_status_t prepare_impl(nufds_plan* p) {
+nufds_status_t prepare_twiddles(nufds_plan* p, bool fft1, bool band) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     const nufds_plan_info_t& g = p->info;
     // every transform must have a pass plan; create the twiddle tables its passes read, so that
     // execute only enqueues kernels
     const int axes[4][5] = {{0, g.nx, g.ny, g.nx, 0}, {1, g.ny, g.nx, g.nx, 0}, {0, g.mx, g.my, g.mx, 1},
                             {1, g.my, g.mx, g.mx, 1}};
-    for (const auto& a : axes) {
+    for (int i = fft1 ? 0 : 2; i < (band ? 4 : 2); ++i) {
+        const auto& a = axes[i];
         AxisPlan ap;
         if (!build_axis(a[0], a[1], a[2], a[3], a[4] ? 1 : -1, a[4], lim, &ap))
             return fail(NUFDS_ERR_UNSUPPORTED, "no FFT pass plan for a transform of length " + std::to_string(a[1]));
@@ -703,7 +689,20 @@ static nufds_status_t prepare_impl(nufds_plan* p) {
                 NUFDS_TRY(twiddle_table<R>(p, d.Lf, &t));
         }
     }
-    // chirp vectors
+    return NUFDS_OK;
+}
+
+template nufds_status_t run_fft1<float>(nufds_plan*, const void*, void*, void*, hipStream_t);
+template nufds_status_t run_fft1<double>(nufds_plan*, const void*, void*, void*, hipStream_t);
+template nufds_status_t run_band<float>(nufds_plan*, const void*, void*, hipStream_t);
+template nufds_status_t run_band<double>(nufds_plan*, const void*, void*, hipStream_t);
+template nufds_status_t prepare_twiddles<float>(nufds_plan*, bool, bool);
+template nufds_status_t prepare_twiddles<double>(nufds_plan*, bool, bool);
+
+template <typename R>
+static nufds_status_t prepare_impl(nufds_plan* p) {
+    NUFDS_TRY(prepare_twiddles<R>(p, true, true));
+    const nufds_plan_info_t& g = p->info;
     std::vector<double> re, im;
     chirp_vector(g.mx, g.nx, p->pitch, p->wavelength, p->z, re, im);
     NUFDS_TRY(upload_complex<R>(p->chirp_x, re, im));
@@ -720,11 +719,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     if (precision != NUFDS_C64 && precision != NUFDS_C128) return fail(NUFDS_ERR_INVALID_ARG, "unknown precision");
     nufds_plan_info_t g;
     NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z, view, flags, opt, &g));
-    if (g.mx > kMaxLen || g.my > kMaxLen || nx > kMaxLen || ny > kMaxLen || !smooth5(nx) || !smooth5(ny))
-        return fail(NUFDS_ERR_UNSUPPORTED, "sizes must be 5-smooth and at most 65536");
-    const int64_t kMaxArray = (int64_t)1 << 31;  // the FFT passes index elements with 32-bit integers
-    if ((int64_t)nx * ny >= kMaxArray || (int64_t)g.mx * g.my >= kMaxArray || (int64_t)g.sx * g.sy >= kMaxArray)
-        return fail(NUFDS_ERR_UNSUPPORTED, "hologram, FrT and output arrays must hold fewer than 2^31 elements");
+    NUFDS_TRY(check_sizes(g));
     nufds_plan* p = new (std::nothrow) nufds_plan();
     if (!p) return fail(NUFDS_ERR_OUT_OF_MEMORY, "host allocation failed");
     p->info = g;
@@ -737,6 +732,8 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     p->esize = precision == NUFDS_C64 ? 8 : 16;
     p->tile_cap = tile_override();
     p->col_w = col_w_override();
+    p->twiddles = std::make_shared<TwiddleCache>();
+    p->twiddles->esize = p->esize;
     auto bail = [&](nufds_status_t st) {
         std::string msg = nufds_last_error();
         plan_free(p);
@@ -754,9 +751,8 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     // stretch-map table: quadrant |k_g| <= min(band extent, stretch extent) per axis
     const double s = wavelength / (2.0 * pitch);
     if (!(flags & NUFDS_FLAG_NO_STRETCH)) {
-        const double ext = stretch_extent(s);
-        const int kmx = (int)std::floor(ext * nx * pitch / wavelength) + 2;
-        const int kmy = (int)std::floor(ext * ny * pitch / wavelength) + 2;
+        int kmx, kmy;
+        table_extent(wavelength, pitch, nx, ny, &kmx, &kmy);
         const int bx = std::max(std::abs(g.kcx - g.mx / 2), std::abs(g.kcx + g.mx / 2 - 1));
         const int by = std::max(std::abs(g.kcy - g.my / 2), std::abs(g.kcy + g.my / 2 - 1));
         p->kxt = std::min(bx, kmx);
@@ -796,6 +792,8 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
 
 // ------------------------------------------------------------------ C ABI
 
+using namespace nufds;
+
 extern "C" {
 
 nufds_status_t nufds_plan_geometry(double wavelength, double pitch, int32_t nx, int32_t ny, double z,
@@ -823,18 +821,26 @@ nufds_status_t nufds_plan_info(nufds_plan_t plan, nufds_plan_info_t* out) {
     return NUFDS_OK;
 }
 
-nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_out, void* stream) {
-    if (!plan || !d_hologram || !d_out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
-    if (d_hologram == d_out) return fail(NUFDS_ERR_INVALID_ARG, "output aliases the hologram");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+// Shared by nufds_execute and nufds_execute_spectrum: the one-execute-in-flight rule, timing
+// bookkeeping and the completion event; d_hologram NULL means spec already holds the spectrum.
+static nufds_status_t execute_common(nufds_plan_t plan, const void* d_hologram, const void* spec, void* d_out,
+                                     hipStream_t s) {
     if (plan->has_run && s != plan->last_stream) {
         hipError_t q = hipEventQuery(plan->done);
         if (q == hipErrorNotReady) return fail(NUFDS_ERR_BUSY, "previous execute still running on another stream");
         if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
     }
     plan->recording = plan->timed_execs < plan->timing_cap;
-    nufds_status_t st = plan->prec == NUFDS_C64 ? execute_impl<float>(plan, d_hologram, d_out, s)
-                                                : execute_impl<double>(plan, d_hologram, d_out, s);
+    nufds_status_t st = NUFDS_OK;
+    if (plan->prec == NUFDS_C64) {
+        if (d_hologram) st = run_fft1<float>(plan, d_hologram, plan->spec.p, plan->work1.p, s);
+        if (st == NUFDS_OK) st = run_band<float>(plan, spec, d_out, s);
+    } else {
+        if (d_hologram) st = run_fft1<double>(plan, d_hologram, plan->spec.p, plan->work1.p, s);
+        if (st == NUFDS_OK) st = run_band<double>(plan, spec, d_out, s);
+    }
     if (plan->recording) ++plan->timed_execs;
     plan->recording = false;
     if (st != NUFDS_OK) return st;
@@ -842,6 +848,23 @@ nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_
     plan->last_stream = s;
     plan->has_run = true;
     return NUFDS_OK;
+}
+
+extern "C" {
+
+nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_out, void* stream) {
+    if (!plan || !d_hologram || !d_out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    if (d_hologram == d_out) return fail(NUFDS_ERR_INVALID_ARG, "output aliases the hologram");
+    return execute_common(plan, d_hologram, plan->spec.p, d_out, static_cast<hipStream_t>(stream));
+}
+
+nufds_status_t nufds_execute_spectrum(nufds_plan_t plan, nufds_spectrum_t spectrum, void* d_out, void* stream) {
+    if (!plan || !spectrum || !d_out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    if (spectrum->nx != plan->info.nx || spectrum->ny != plan->info.ny || spectrum->prec != plan->prec ||
+        spectrum->wavelength != plan->wavelength || spectrum->pitch != plan->pitch ||
+        (spectrum->flags & NUFDS_FLAG_CONVERGING) != (plan->flags & NUFDS_FLAG_CONVERGING))
+        return fail(NUFDS_ERR_INVALID_ARG, "spectrum and plan differ in size, wavelength, pitch, precision or sign");
+    return execute_common(plan, nullptr, spectrum->spec.p, d_out, static_cast<hipStream_t>(stream));
 }
 
 nufds_status_t nufds_debug_copy(nufds_plan_t plan, int32_t which, void* d_dst, uint64_t* bytes, void* stream) {

@@ -585,7 +585,7 @@ __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& 
 
 // NBMAX: butterflies a thread holds per stage.  NBMAX = 1 is the small-tile variant (one butterfly
 // per thread, more threads, fewer live registers); the other variant serves long single-pass rows.
-template <typename R, int MAXE, int NBMAX, int MAXT>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
                                                         const cpx<R>* __restrict__ tw,
                                                         const cpx<R>* __restrict__ twf,
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     int Ns = 1;
     const int sg = d.sign;
 #define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, F, L, C>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg, tid, T)
-    if (!d.chain) {
+    if constexpr (!CHAINP) {
         for (int s = 0; s < nst; ++s) {
             const int r = d.rad[s];
             const bool first = s == 0, last = s == nst - 1;
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
             Ns *= r;
         }
         return;
-    }
+    } else {
     for (int s = 0; s < nst; ++s) {
         const int r = d.rad[s];
         const bool first = s == 0, last = s == nst - 1;
@@ -652,13 +652,14 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
             fft_stage_r<R, MAXE, NBMAX, false, false, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
         Ns *= r;
     }
+    }
 }
 
-template <typename R, int MAXE, int NBMAX, int MAXT>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP>
 static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                                  const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
     static bool attr_set = false;
-    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT>;
+    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -675,9 +676,13 @@ static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, cons
 template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                        const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
-    if (d.one_bfly)
-        return launch_variant<R, OneBflyElems<R>::value, 1, OneBflyThreads<R>::value>(d, ld, st, tw, twf, chainvec, chainscale, s);
-    return launch_variant<R, MaxElems<R>::value, 64, 1024>(d, ld, st, tw, twf, chainvec, chainscale, s);
+    constexpr int OE = OneBflyElems<R>::value, OT = OneBflyThreads<R>::value, ME = MaxElems<R>::value;
+    if (d.chain) {
+        if (d.one_bfly) return launch_variant<R, OE, 1, OT, true>(d, ld, st, tw, twf, chainvec, chainscale, s);
+        return launch_variant<R, ME, 64, 1024, true>(d, ld, st, tw, twf, chainvec, chainscale, s);
+    }
+    if (d.one_bfly) return launch_variant<R, OE, 1, OT, false>(d, ld, st, tw, twf, chainvec, chainscale, s);
+    return launch_variant<R, ME, 64, 1024, false>(d, ld, st, tw, twf, chainvec, chainscale, s);
 }
 
 template hipError_t launch_pass<float>(const PassDesc&, const LoadPlain<float>&,

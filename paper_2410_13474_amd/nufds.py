@@ -57,6 +57,11 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("ms", ctypes.c_double), ("bytes", ctypes.c_uint64)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_frt_size", ctypes.c_int32), ("max_view_size", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_uint64)]
+
+
 class NufdsError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"libnufds status {status}: {msg}")
@@ -87,6 +92,18 @@ _SIGNATURES = {
     "nufds_synth_hologram": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                                             ctypes.c_void_p]),
+    "nufds_spectrum_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "nufds_spectrum_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nufds_execute_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "nufds_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ServerOptions)]),
+    "nufds_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(View),
+                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "nufds_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "nufds_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
+    "nufds_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "nufds_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "nufds_last_error": (ctypes.c_char_p, []),
 }
@@ -185,6 +202,14 @@ class Plan:
         import torch
         return torch.complex64 if self.precision == C64 else torch.complex128
 
+    def execute_spectrum(self, spectrum: "Spectrum", out, stream=None) -> None:
+        """Enqueue the reconstruction from a cached spectrum (no forward FFT) into ``out``."""
+        i = self.info
+        if out.dtype != self.dtype or tuple(out.shape) != (i["sy"], i["sx"]) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of the plan's output shape and precision")
+        _check(self._lib.nufds_execute_spectrum(self._h, spectrum._h, ctypes.c_void_p(out.data_ptr()),
+                                                _stream_handle(stream)))
+
     def execute(self, hologram, out, stream=None) -> None:
         """Enqueue the reconstruction of device tensor ``hologram`` into ``out``."""
         import torch
@@ -261,3 +286,83 @@ def synth_hologram(points, nx, ny, pitch, wavelength, out, stream=None) -> None:
     _check(lib.nufds_synth_hologram(pts.ctypes.data_as(ctypes.c_void_p), int(pts.shape[0]), int(nx), int(ny),
                                     float(pitch), float(wavelength), prec, ctypes.c_void_p(out.data_ptr()),
                                     _stream_handle(stream)))
+
+
+class Spectrum:
+    """The forward FFT of one hologram, cached on the device (computed when constructed)."""
+
+    def __init__(self, hologram, wavelength, pitch, flags=0, stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        if hologram.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("hologram must be complex64 or complex128")
+        if not (hologram.is_cuda and hologram.is_contiguous() and hologram.dim() == 2):
+            raise ValueError("hologram must be a contiguous 2-D device tensor")
+        self.precision = C64 if hologram.dtype == torch.complex64 else C128
+        self.ny, self.nx = int(hologram.shape[0]), int(hologram.shape[1])
+        self.wavelength, self.pitch, self.flags = float(wavelength), float(pitch), int(flags)
+        handle = ctypes.c_void_p()
+        _check(lib.nufds_spectrum_create(ctypes.byref(handle), self.wavelength, self.pitch, self.nx, self.ny,
+                                         self.precision, self.flags, ctypes.c_void_p(hologram.data_ptr()),
+                                         _stream_handle(stream)))
+        self._h = handle
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nufds_spectrum_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Partial-view server over cached spectra: submit() queues, wait() returns the latency in ms."""
+
+    def __init__(self, precision="c64", max_frt_size=8192, max_view_size=4096, max_inflight=4,
+                 max_workspace_bytes=0):
+        lib = load()
+        self._lib = lib
+        self.precision = {"c64": C64, "c128": C128}[precision]
+        opt = ServerOptions(self.precision, int(max_frt_size), int(max_view_size), int(max_inflight),
+                            int(max_workspace_bytes))
+        handle = ctypes.c_void_p()
+        _check(lib.nufds_server_create(ctypes.byref(handle), ctypes.byref(opt)))
+        self._h = handle
+
+    def submit(self, spectrum: Spectrum, z, out, view=None, flags=0) -> int:
+        """Queue one view of ``spectrum`` at distance ``z`` into device tensor ``out``; returns a ticket."""
+        v = _view(view)
+        if not (out.is_cuda and out.is_contiguous()):
+            raise ValueError("out must be a contiguous device tensor")
+        t = ctypes.c_uint64()
+        _check(self._lib.nufds_server_submit(self._h, spectrum._h, float(z), ctypes.byref(v) if v is not None else None,
+                                             int(flags), ctypes.c_void_p(out.data_ptr()), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(state, latency_ms): state 0 queued/running, 1 done, 2 failed."""
+        st, lat = ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.nufds_server_poll(self._h, int(ticket), ctypes.byref(st), ctypes.byref(lat)))
+        return int(st.value), float(lat.value)
+
+    def wait(self, ticket: int) -> float:
+        """Block until the request ends; returns its latency in ms (raises on a failed request)."""
+        lat = ctypes.c_double()
+        _check(self._lib.nufds_server_wait(self._h, int(ticket), ctypes.byref(lat)))
+        return float(lat.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nufds_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

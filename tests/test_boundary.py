@@ -139,6 +139,43 @@ def test_null_arguments_are_rejected():
     assert b"invalid" in lib.nufds_last_error()
 
 
+def test_serving_entry_points_reject_invalid_arguments():
+    """Every check below fails before any HIP call, so it runs without a GPU."""
+    lib = N.load()
+    h = ctypes.c_void_p(1234)
+    dummy = ctypes.c_void_p(4096)
+    # spectrum: NULL out, NULL hologram, unknown precision, flags other than CONVERGING, odd size
+    assert lib.nufds_spectrum_create(None, 0.5e-6, 0.5e-6, 64, 64, 0, 0, dummy, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_spectrum_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, 0, 0, None, None) == N.ERR_INVALID_ARG
+    assert h.value is None
+    assert lib.nufds_spectrum_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, 5, 0, dummy, None) == N.ERR_INVALID_ARG
+    for flags in (N.FLAG_NO_STRETCH, N.FLAG_NO_REMAP, 64):
+        assert lib.nufds_spectrum_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, 0, flags, dummy,
+                                         None) == N.ERR_INVALID_ARG
+    assert lib.nufds_spectrum_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 63, 64, 0, 0, dummy, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_spectrum_create(ctypes.byref(h), 0.5e-6, 0.2e-6, 64, 64, 0, 0, dummy, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_spectrum_destroy(None) == N.OK
+    assert lib.nufds_execute_spectrum(None, None, None, None) == N.ERR_INVALID_ARG
+    # server: NULL handles and options out of range
+    assert lib.nufds_server_create(None, None) == N.ERR_INVALID_ARG
+    bad = [N.ServerOptions(7, 1024, 512, 2, 0), N.ServerOptions(0, 0, 512, 2, 0),
+           N.ServerOptions(0, 1023, 512, 2, 0), N.ServerOptions(0, 1024, 0, 2, 0),
+           N.ServerOptions(0, 1024, 512, 0, 0), N.ServerOptions(0, 1 << 17, 512, 2, 0)]
+    for opt in bad:
+        h = ctypes.c_void_p(1234)
+        assert lib.nufds_server_create(ctypes.byref(h), ctypes.byref(opt)) == N.ERR_INVALID_ARG
+        assert h.value is None
+    # a workspace limit below one slot is an out-of-memory refusal, decided on the host
+    opt = N.ServerOptions(0, 1024, 512, 2, 1 << 20)
+    assert lib.nufds_server_create(ctypes.byref(h), ctypes.byref(opt)) == N.ERR_OUT_OF_MEMORY
+    t = ctypes.c_uint64()
+    assert lib.nufds_server_submit(None, None, 1e-3, None, 0, None, ctypes.byref(t)) == N.ERR_INVALID_ARG
+    st, lat = ctypes.c_int32(), ctypes.c_double()
+    assert lib.nufds_server_poll(None, 1, ctypes.byref(st), ctypes.byref(lat)) == N.ERR_INVALID_ARG
+    assert lib.nufds_server_wait(None, 1, ctypes.byref(lat)) == N.ERR_INVALID_ARG
+    assert lib.nufds_server_destroy(None) == N.OK
+
+
 def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(N, "_lib", None)
     monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "missing.so"))
