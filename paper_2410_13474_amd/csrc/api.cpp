@@ -267,7 +267,8 @@ static nufds_status_t twiddle_table(nufds_plan* p, int L, const cpx<R>** out) {
     return NUFDS_OK;
 }
 
-// The chirp exp(+i k xi^2 / 2z) of Eq. 2 at xi = (n - M/2) N D / M, phase in float64 reduced mod 2 pi.
+// The chirp exp(+i k xi^2 / 2z) of Eq. 2 at xi = (n - M/2) N D / M, phase in float64 reduced mod 2 pi,
+// times 1/M: the normalisation of the centred inverse DFT that precedes it in the chain.
 void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::vector<double>& re,
                   std::vector<double>& im) {
     re.resize(M);
@@ -278,8 +279,8 @@ void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::
         double cyc = xi * xi * cycles_per_m2;
         cyc -= std::floor(cyc);
         const double ph = 2.0 * M_PI * cyc;
-        re[n] = std::cos(ph);
-        im[n] = std::sin(ph);
+        re[n] = std::cos(ph) / M;
+        im[n] = std::sin(ph) / M;
     }
 }
 
@@ -511,7 +512,7 @@ static uint64_t pass_bytes(const PassDesc& d, size_t esize) { return 2ull * d.ro
 template <typename R>
 static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& d, const void* in, void* out,
                                int load_conj, int load_sign, int store_sign, R store_scale,
-                               const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+                               const cpx<R>* chainvec, hipStream_t s) {
     const cpx<R>* tw;
     nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
     if (st != NUFDS_OK) return st;
@@ -520,10 +521,10 @@ static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& 
         st = twiddle_table<R>(p, d.Lf, &twf);
         if (st != NUFDS_OK) return st;
     }
-    LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1)};
-    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_sign, store_scale};
+    LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1), (!load_conj && !load_sign) ? 1 : 0};
+    StorePlain<R> sto{static_cast<cpx<R>*>(out), store_sign, store_scale, (!store_sign && store_scale == R(1)) ? 1 : 0};
     NUFDS_TRY(timing_begin(p, name, pass_bytes(d, sizeof(cpx<R>)), s));
-    NUFDS_HIP_TRY((launch_pass<R>(d, ld, sto, tw, twf, chainvec, chainscale, s)));
+    NUFDS_HIP_TRY((launch_pass<R>(d, ld, sto, tw, twf, chainvec, s)));
     return timing_end(p, s);
 }
 
@@ -579,18 +580,18 @@ nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, h
     if (!build_axis(0, nx, ny, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram row length");
     const R sgx = ((nx / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, s));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, s));
     }
     if (!build_axis(1, ny, nx, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram column length");
     const R sgy = ((ny / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, s));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, s));
     }
     return NUFDS_OK;
 }
@@ -614,23 +615,23 @@ nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_
     // the stretch-gather runs as a kernel of its own (2-D tiles, each quadrant table entry read once)
     NUFDS_TRY(run_stretch_gather<R>(p, spec, w2, s));
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "xop", ap.passes[0], w2, w1, 0, 0, 1, R(1), cxv, R(1) / R(mx), s));
+        NUFDS_TRY(run_pass<R>(p, "xop", ap.passes[0], w2, w1, 0, 0, 1, R(1), cxv, s));
         res = w1;
     } else {
-        NUFDS_TRY(run_pass<R>(p, "xop_a", ap.passes[0], w2, w1, 0, 0, 0, R(1), nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_ba", ap.passes[1], w1, w2, 0, 0, 0, R(1), cxv, R(1) / R(mx), s));
-        NUFDS_TRY(run_pass<R>(p, "xop_b", ap.passes[2], w2, w1, 0, 0, 1, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "xop_a", ap.passes[0], w2, w1, 0, 0, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "xop_ba", ap.passes[1], w1, w2, 0, 0, 0, R(1), cxv, s));
+        NUFDS_TRY(run_pass<R>(p, "xop_b", ap.passes[2], w2, w1, 0, 0, 1, R(1), nullptr, s));
         res = w1;
     }
     // and along y
     if (!build_axis(1, my, mx, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), cyv, R(1) / R(my), s));
+        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), cyv, s));
     } else {
         void* oth = (res == w1) ? w2 : w1;
-        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, R(1), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), cyv, R(1) / R(my), s));
-        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, R(1), s));
+        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), cyv, s));
+        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, s));
         res = oth;
     }
     p->result = res;

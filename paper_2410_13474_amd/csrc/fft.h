@@ -34,9 +34,11 @@ enum PassKind : int {
     K_ROWBA = 6, K_COLBA = 7 // B pass of one transform, chain multiply, A pass of the next
 };
 
-// LDS index with one pad element every 32: breaks the power-of-two strides of the first
-// Stockham stage and of the column tiles across the LDS banks.
-__host__ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+// LDS index of tile element i = n W + w.  Narrow tiles (PAD) insert one pad element every 32 to
+// break the power-of-two strides of the Stockham writes across the LDS banks; tiles of 8 or more
+// columns keep adjacent lanes on adjacent words and need none.
+template <bool PAD>
+__host__ __device__ __forceinline__ int lds_index(int i) { return PAD ? i + (i >> 5) : i; }
 __host__ __device__ __forceinline__ int lds_elems(int n) { return n + (n >> 5) + 1; }
 
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, each with its own L2
@@ -83,6 +85,7 @@ struct LoadPlain {
     int conj;
     int sign_axis;
     R scale;
+    int plain;  // no conjugation, sign or scale: the load is a copy
 };
 
 // ---------------------------------------------------------------- stores
@@ -93,13 +96,14 @@ struct StorePlain {
     cpx<R>* out;
     int sign_axis;
     R scale;
+    int plain;  // no sign or scale: the store is a copy
 };
 
-// Element-wise factor between the two transforms of a chain pass: vec[n cn + w cw + c0] * scale.
+// Element-wise factor between the two transforms of a chain pass: vec[n cn + w cw + c0] (the
+// caller folds any scale into the vector).
 template <typename R>
 struct ChainMul {
     const cpx<R>* vec;
-    R scale;
 };
 
 // ---------------------------------------------------------------- host side
@@ -108,7 +112,7 @@ struct FftTables;  // per-length twiddle tables, owned by a plan
 
 template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
-                       const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s);
+                       const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s);
 
 // Radix sequence of a 5-smooth length with the fewest stages (radices 2-6, 8-10, 12, 15, 16 up to
 // max_radix); false if there is none.

@@ -420,7 +420,7 @@ struct StageNb {
 // order that makes their global accesses contiguous (j fastest for transforms that run along memory,
 // w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
 // precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
-template <typename R, int RAD, int MAXE, int NBMAX, bool FIRST, bool LAST, bool CHAIN>
+template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN>
 __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
                                           const StorePlain<R>& st, const ChainMul<R>& ch,
                                           const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
@@ -439,9 +439,10 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     const int lw = d.logW, W = 1 << lw;
     const int LR = L / RAD;
     const int B = LR << lw;
-    const int tstride = L / (Ns * RAD);
-    const float invNs = 1.0f / (float)Ns;
-    const float invLR = 1.0f / (float)LR;
+    // the first stage has Ns = 1 (q = j, k = 0), the last Ns = L / RAD (q = 0, k = j)
+    const int tstride = (FIRST || LAST) ? 1 : L / (Ns * RAD);
+    const float invNs = (FIRST || LAST) ? 1.0f : __builtin_amdgcn_rcpf((float)Ns);  // fdiv corrects the last bit
+    const float invLR = __builtin_amdgcn_rcpf((float)LR);
     const bool jfast = FIRST ? m.in_nfast : (LAST ? m.out_nfast : (W == 1));
     cpx<R> v[NB][RAD];
     cpx<R> cw[NB];
@@ -454,8 +455,8 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
         int j, w;
         if (jfast) { w = fdiv(b, LR, invLR); j = b - w * LR; }
         else { w = b & (W - 1); j = b >> lw; }
-        const int q = fdiv(j, Ns, invNs);
-        const int k = j - q * Ns;
+        const int q = FIRST ? j : (LAST ? 0 : fdiv(j, Ns, invNs));
+        const int k = FIRST ? 0 : (LAST ? j : j - q * Ns);
         if (!FIRST) cw[i] = load_at<R>(uniform_base(tw), (uint32_t)(k * tstride) * ES);
         if (FIRST) {
             const bool valid = b0 < B && w < m.wvalid;
@@ -465,7 +466,7 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
                 v[i][t] = load_at<R>(uniform_base(ld.in + ((int64_t)ib_s + (int64_t)(t * LR) * m.isn)), lo);
         } else {
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_pad(((j + t * LR) << lw) + w)];
+            for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_index<PAD>(((j + t * LR) << lw) + w)];
         }
         if (CHAIN) {
             // last stage of the first transform of a chain pass: outputs sit at natural positions
@@ -493,17 +494,19 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
             int j, w;
             if (jfast) { w = fdiv(b, LR, invLR); j = b - w * LR; }
             else { w = b & (W - 1); j = b >> lw; }
-            const int q = fdiv(j, Ns, invNs);
-            const int k = j - q * Ns;
+            const int q = FIRST ? j : (LAST ? 0 : fdiv(j, Ns, invNs));
+            const int k = FIRST ? 0 : (LAST ? j : j - q * Ns);
             if (FIRST) {
-                // fused load work: conjugation, (-1)^(axis index) centring, scale; padding lanes give 0
-                const R sc = (w < m.wvalid) ? ld.scale : R(0);
-                const int par = (j * m.an + w * m.aw + m.a0) & 1;
+                // fused load work: conjugation, (-1)^(axis index) centring, scale (padding lanes
+                // hold finite values of valid rows; their transforms are never stored)
+                if (!ld.plain) {
+                    const int par = (j * m.an + w * m.aw + m.a0) & 1;
 #pragma unroll
-                for (int t = 0; t < RAD; ++t) {
-                    const bool flip = ld.sign_axis && ((par + t * LR * m.an) & 1);
-                    const R f = flip ? -sc : sc;
-                    v[i][t] = mk(v[i][t].x * f, (ld.conj ? -v[i][t].y : v[i][t].y) * f);
+                    for (int t = 0; t < RAD; ++t) {
+                        const bool flip = ld.sign_axis && ((par + t * LR * m.an) & 1);
+                        const R f = flip ? -ld.scale : ld.scale;
+                        v[i][t] = mk(v[i][t].x * f, (ld.conj ? -v[i][t].y : v[i][t].y) * f);
+                    }
                 }
             } else {
                 cpx<R> c = cw[i];
@@ -534,39 +537,45 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
                         }
                     }
                     const uint32_t lo = (uint32_t)(j * m.osn + w * m.osw) * ES;
-                    const int par = (j * m.bn + w * m.bw + m.b0) & 1;
+                    if (!st.plain) {
+                        const int par = (j * m.bn + w * m.bw + m.b0) & 1;
+#pragma unroll
+                        for (int t = 0; t < RAD; ++t) {
+                            const bool flip = st.sign_axis && ((par + t * LR * m.bn) & 1);
+                            const R f = flip ? -st.scale : st.scale;
+                            v[i][SmallDft<R, RAD>::perm(t)] = v[i][SmallDft<R, RAD>::perm(t)] * f;
+                        }
+                    }
 #pragma unroll
                     for (int t = 0; t < RAD; ++t) {
-                        const bool flip = st.sign_axis && ((par + t * LR * m.bn) & 1);
-                        const R f = flip ? -st.scale : st.scale;
                         store_at<R>(uniform_base(st.out + ((int64_t)ob_s + (int64_t)(t * LR) * m.osn)), lo,
-                                 v[i][SmallDft<R, RAD>::perm(t)] * tf * f);
-                        tf = tf * step;
+                                 m.twiddle ? v[i][SmallDft<R, RAD>::perm(t)] * tf : v[i][SmallDft<R, RAD>::perm(t)]);
+                        if (m.twiddle) tf = tf * step;
                     }
                 }
             } else if (CHAIN) {
 #pragma unroll
                 for (int t = 0; t < RAD; ++t)
-                    lds[lds_pad(((j + t * LR) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)] * cv[i][t] * ch.scale;
+                    lds[lds_index<PAD>(((j + t * LR) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)] * cv[i][t];
             } else {
                 const int base = q * Ns * RAD + k;
 #pragma unroll
                 for (int t = 0; t < RAD; ++t)
-                    lds[lds_pad(((base + t * Ns) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)];
+                    lds[lds_index<PAD>(((base + t * Ns) << lw) + w)] = v[i][SmallDft<R, RAD>::perm(t)];
             }
         }
     }
     if (!LAST) __syncthreads();
 }
 
-template <typename R, int MAXE, int NBMAX, bool FIRST, bool LAST, bool CHAIN>
+template <typename R, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN>
 __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m,
                                             const LoadPlain<R>& ld, const StorePlain<R>& st, const ChainMul<R>& ch,
                                             const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
                                             int sign, int tid, int T) {
 #define NUFDS_STAGE(RR)                                                                             \
     if constexpr ((RR) <= MAXE)                                                                     \
-        fft_stage<R, RR, MAXE, NBMAX, FIRST, LAST, CHAIN>(lds, d, m, ld, st, ch, tw, twf, Ns, sign, tid, T)
+        fft_stage<R, RR, MAXE, NBMAX, PAD, FIRST, LAST, CHAIN>(lds, d, m, ld, st, ch, tw, twf, Ns, sign, tid, T)
     switch (r) {
         case 16: NUFDS_STAGE(16); break;
         case 8: NUFDS_STAGE(8); break;
@@ -585,11 +594,11 @@ __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& 
 
 // NBMAX: butterflies a thread holds per stage.  NBMAX = 1 is the small-tile variant (one butterfly
 // per thread, more threads, fewer live registers); the other variant serves long single-pass rows.
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
                                                         const cpx<R>* __restrict__ tw,
                                                         const cpx<R>* __restrict__ twf,
-                                                        const cpx<R>* __restrict__ chainvec, R chainscale) {
+                                                        const cpx<R>* __restrict__ chainvec) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x, T = blockDim.x;
@@ -612,13 +621,13 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     const TileMap m = tile_map(d, ta, tb);
     const int nst = d.nst;
 
-    const ChainMul<R> ch{chainvec, chainscale};
+    const ChainMul<R> ch{chainvec};
 
     // transform 1: stage 0 reads global memory; the last stage writes global memory, or, in a chain
     // pass, multiplies by the chain vector (the chirp of Eq. 2) on its way to LDS
     int Ns = 1;
     const int sg = d.sign;
-#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, F, L, C>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg, tid, T)
+#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, PAD, F, L, C>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg, tid, T)
     if constexpr (!CHAINP) {
         for (int s = 0; s < nst; ++s) {
             const int r = d.rad[s];
@@ -647,51 +656,59 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     for (int s = 0; s < nst; ++s) {
         const int r = d.rad[s];
         if (s == nst - 1)
-            fft_stage_r<R, MAXE, NBMAX, false, true, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+            fft_stage_r<R, MAXE, NBMAX, PAD, false, true, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
         else
-            fft_stage_r<R, MAXE, NBMAX, false, false, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+            fft_stage_r<R, MAXE, NBMAX, PAD, false, false, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
         Ns *= r;
     }
     }
 }
 
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD>
 static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
-                                 const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+                                 const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     static bool attr_set = false;
-    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP>;
+    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);
+    const size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);  // padded size covers both layouts
     const int ga = d.xcd_rows ? kXcds * ((d.tiles_a + kXcds - 1) / kXcds) : d.tiles_a;
     dim3 grid(d.tiles_b, ga), block(d.nthreads);
-    hipLaunchKernelGGL(kern, grid, block, shm, s, d, ld, st, tw, twf, chainvec, chainscale);
+    hipLaunchKernelGGL(kern, grid, block, shm, s, d, ld, st, tw, twf, chainvec);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
-                       const cpx<R>* twf, const cpx<R>* chainvec, R chainscale, hipStream_t s) {
+                       const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     constexpr int OE = OneBflyElems<R>::value, OT = OneBflyThreads<R>::value, ME = MaxElems<R>::value;
+    // tiles of 8 or more columns keep their lanes on consecutive LDS words without padding; the
+    // several-butterflies variant serves long rows (narrow tiles) only
+    const bool pad = d.W < 8;
     if (d.chain) {
-        if (d.one_bfly) return launch_variant<R, OE, 1, OT, true>(d, ld, st, tw, twf, chainvec, chainscale, s);
-        return launch_variant<R, ME, 64, 1024, true>(d, ld, st, tw, twf, chainvec, chainscale, s);
+        if (d.one_bfly) {
+            if (pad) return launch_variant<R, OE, 1, OT, true, true>(d, ld, st, tw, twf, chainvec, s);
+            return launch_variant<R, OE, 1, OT, true, false>(d, ld, st, tw, twf, chainvec, s);
+        }
+        return launch_variant<R, ME, 64, 1024, true, true>(d, ld, st, tw, twf, chainvec, s);
     }
-    if (d.one_bfly) return launch_variant<R, OE, 1, OT, false>(d, ld, st, tw, twf, chainvec, chainscale, s);
-    return launch_variant<R, ME, 64, 1024, false>(d, ld, st, tw, twf, chainvec, chainscale, s);
+    if (d.one_bfly) {
+        if (pad) return launch_variant<R, OE, 1, OT, false, true>(d, ld, st, tw, twf, chainvec, s);
+        return launch_variant<R, OE, 1, OT, false, false>(d, ld, st, tw, twf, chainvec, s);
+    }
+    return launch_variant<R, ME, 64, 1024, false, true>(d, ld, st, tw, twf, chainvec, s);
 }
 
 template hipError_t launch_pass<float>(const PassDesc&, const LoadPlain<float>&,
                                                          const StorePlain<float>&, const cpx<float>*,
-                                                         const cpx<float>*, const cpx<float>*, float, hipStream_t);
+                                                         const cpx<float>*, const cpx<float>*, hipStream_t);
 template hipError_t launch_pass<double>(const PassDesc&, const LoadPlain<double>&,
                                                            const StorePlain<double>&, const cpx<double>*,
-                                                           const cpx<double>*, const cpx<double>*, double,
-                                                           hipStream_t);
+                                                           const cpx<double>*, const cpx<double>*, hipStream_t);
 // Radix sequence of a 5-smooth length with the fewest stages (then the largest leading radices)
 // from the radices the kernel implements; radices above max_radix are not used.
 bool factor_radices(int L, int* nst, int* rad, int max_radix) {

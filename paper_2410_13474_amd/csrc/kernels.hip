@@ -1,6 +1,8 @@
 // Map-table, output-gather and test-input kernels of libnufds (gfx950).
 #include "kernels.h"
 
+#include <climits>
+
 #include "special.h"
 
 namespace nufds {
@@ -103,48 +105,168 @@ __device__ __forceinline__ cpx<R> keys_spectrum(const cpx<R>* __restrict__ spec,
 // k_g = K_c + k' - M/2) is the hologram spectrum Keys-interpolated at the pre-image of k_g.  The map
 // is odd in each axis, so the pre-image of (+-|k_gx|, +-|k_gy|) is (+-P_x, +-P_y) from one table entry.
 // Output carries the (-1)^(k'_x) centring sign of the inverse transform that follows.
+// Keys 4 x 4 from a window of the spectrum held in LDS ([rows][wx]; taps at r0..r0+3, c0..c0+3).
+template <typename R>
+__device__ __forceinline__ cpx<R> keys_window(const cpx<R>* w, int wx, int c0, int r0, const R* kx, const R* ky) {
+    cpx<R> acc = mk(R(0), R(0));
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const cpx<R>* row = w + (r0 + b) * wx + c0;
+        const cpx<R> racc = row[0] * kx[0] + row[1] * kx[1] + row[2] * kx[2] + row[3] * kx[3];
+        acc = acc + racc * ky[b];
+    }
+    return acc;
+}
+
+// One workgroup covers a 16 x 16 tile of quadrant entries.  The pre-images of a tile lie within about
+// 20 x 20 spectral samples (the inverse stretch contracts), so the workgroup first copies the four
+// mirrored spectrum windows under its stencils into LDS with plain row loads and then interpolates
+// from LDS: each spectrum sample is fetched once per tile instead of once per tap, which relieves the
+// texture-address unit that bounds a per-tap gather.  The Keys kernel is even, so the mirror -p uses
+// the weights of p in reverse order on the taps floor(-p) - 1 .. floor(-p) + 2 reflected, i.e. from
+// N - (first tap of p) - 3 on; one set of weights per axis serves all four mirrors.  A tile whose
+// window would not fit (none at the sizes measured) interpolates straight from global memory.
+constexpr int kGatherTile = 16;
+constexpr int kGatherWinX = 32;  // window columns at most (one per lane of half a wave)
+constexpr int kGatherWinY = 24;  // window rows at most
+
 template <typename R>
 __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
-    // consecutive block rows to one XCD (round-robin dispatch): their stencils share L2 lines
+    constexpr int T = kGatherTile, WXM = kGatherWinX, WYM = kGatherWinY, CAP = WXM * WYM;
+    constexpr int RG = 256 / WXM;             // row groups of the fill
+    constexpr int K = (WYM + RG - 1) / RG;    // fill loads per thread and mirror
+    __shared__ cpx<R> win[4][CAP];
+    __shared__ int red[4][4];
+    // consecutive tile rows to one XCD (round-robin dispatch): their windows share L2 lines
     const int nb = gridDim.x;
-    const int nrows = (a.nay + blockDim.y - 1) / blockDim.y;
+    const int nrows = (a.nay + T - 1) / T;
     const int lin = blockIdx.y * nb + blockIdx.x;
     const int xcd = lin % kXcds, slot = lin / kXcds;
     const int per = (nrows + kXcds - 1) / kXcds;
     const int brow = xcd * per + slot / nb;
     if (brow >= nrows) return;
-    const int ax = a.ax0 + (slot % nb) * blockDim.x + threadIdx.x;
-    const int ay = a.ay0 + brow * blockDim.y + threadIdx.y;
-    if (ax >= a.ax0 + a.nax || ay >= a.ay0 + a.nay) return;
+    const int tid = threadIdx.x;
+    const int ax = a.ax0 + (slot % nb) * T + (tid % T);
+    const int ay = a.ay0 + brow * T + tid / T;
+    const bool inr = ax < a.ax0 + a.nax && ay < a.ay0 + a.nay;
     double px, py;
     bool valid;
     if (a.nostretch) {
-        valid = ax <= (a.nx >> 1) && ay <= (a.ny >> 1);
-        px = valid ? ax : 0.0;   // masked entries read the centre (in bounds) and are zeroed
+        valid = inr && ax <= (a.nx >> 1) && ay <= (a.ny >> 1);
+        px = valid ? ax : 0.0;
         py = valid ? ay : 0.0;
     } else {
-        valid = ax <= a.kxt && ay <= a.kyt;
+        valid = inr && ax <= a.kxt && ay <= a.kyt;
         const int64_t e = valid ? (int64_t)ay * (a.kxt + 1) + ax : 0;
         const double tx = a.table[2 * e], ty = a.table[2 * e + 1];
         valid = valid && tx == tx;
-        // masked entries (NaN in the table, or beyond it) read the spectrum centre and are zeroed:
-        // a NaN coordinate must never reach the index arithmetic
+        // masked entries (NaN in the table, or beyond it) never reach the index arithmetic
         px = valid ? tx : 0.0;
         py = valid ? ty : 0.0;
     }
-    // the mirrors are interpolated without branches (a masked entry reads the spectrum centre and
-    // is zeroed), so their loads overlap; only the stores are predicated on the band
+    const int hx = a.nx >> 1, hy = a.ny >> 1;
+    const double fx = floor(px), fy = floor(py);
+    R wgx[4], wgy[4];
+    keys4<R>(R(px - fx), wgx);
+    keys4<R>(R(py - fy), wgy);
+    // first tap of the (+, +) mirror in spectrum indices, and its extent over the tile's valid entries
+    const int ixp = (int)fx - 1 + hx, iyp = (int)fy - 1 + hy;
+    int r0 = valid ? ixp : INT_MAX, r1 = valid ? -ixp : INT_MAX;
+    int r2 = valid ? iyp : INT_MAX, r3 = valid ? -iyp : INT_MAX;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        r0 = min(r0, __shfl_xor(r0, o));
+        r1 = min(r1, __shfl_xor(r1, o));
+        r2 = min(r2, __shfl_xor(r2, o));
+        r3 = min(r3, __shfl_xor(r3, o));
+    }
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = r0;
+        red[tid >> 6][1] = r1;
+        red[tid >> 6][2] = r2;
+        red[tid >> 6][3] = r3;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        r0 = min(r0, red[w][0]);
+        r1 = min(r1, red[w][1]);
+        r2 = min(r2, red[w][2]);
+        r3 = min(r3, red[w][3]);
+    }
+    const bool any = r0 != INT_MAX;  // uniform over the workgroup
+    const int mnx = r0, mxx = -r1, mny = r2, mxy = -r3;
+    // windows: x from mnx (mirror +) or nx - mxx - 3 (mirror -), wx columns; likewise y
+    const int wx = mxx - mnx + 4, wy = mxy - mny + 4;
+    const bool fits = any && wx <= WXM && wy <= WYM;
+    if (fits) {
+        const int c = tid % WXM, rg = tid / WXM;
+        const bool cin = c < wx;
+        cpx<R> tmp[4][K];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int sx = m & 1, sy = m >> 1;
+            const int x0 = sx ? a.nx - mxx - 3 : mnx, y0 = sy ? a.ny - mxy - 3 : mny;
+            int gc = x0 + (cin ? c : 0);
+            gc = gc < 0 ? gc + a.nx : (gc >= a.nx ? gc - a.nx : gc);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int r = rg + k * RG;
+                int gr = y0 + (r < wy ? r : 0);  // branch-free: every thread loads in bounds
+                gr = gr < 0 ? gr + a.ny : (gr >= a.ny ? gr - a.ny : gr);
+                tmp[m][k] = a.spec[(int64_t)gr * a.nx + gc];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int r = rg + k * RG;
+                if (cin && r < wy) win[m][r * wx + c] = tmp[m][k];
+            }
+        __syncthreads();
+    }
     const R scale = valid ? R(1) : R(0);
+    const int c0 = valid ? ixp - mnx : 0, rr0 = valid ? iyp - mny : 0;  // (+) mirror window offsets
 #pragma unroll
     for (int sy = 0; sy < 2; ++sy) {
         const int ky = (sy ? -ay : ay) - a.gy0;
-        const bool yin = ky >= 0 && ky < a.my && !(sy && ay == 0);
+        const bool yin = inr && ky >= 0 && ky < a.my && !(sy && ay == 0);
+        R ky4[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ky4[b] = sy ? wgy[3 - b] : wgy[b];
+        // mirror row offset: (ny - iyp - 3) - (ny - mxy - 3) = mxy - iyp
+        const int r0w = sy ? (valid ? mxy - iyp : 0) : rr0;
 #pragma unroll
         for (int sx = 0; sx < 2; ++sx) {
             const int kx = (sx ? -ax : ax) - a.gx0;
             const bool in = yin && kx >= 0 && kx < a.mx && !(sx && ax == 0);
-            cpx<R> v = keys_spectrum<R>(a.spec, a.nx, a.ny, (sx ? -px : px) + (double)(a.nx >> 1),
-                                        (sy ? -py : py) + (double)(a.ny >> 1));
+            R kx4[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) kx4[b] = sx ? wgx[3 - b] : wgx[b];
+            cpx<R> v;
+            if (fits) {
+                const int c0w = sx ? (valid ? mxx - ixp : 0) : c0;
+                v = keys_window<R>(win[2 * sy + sx], wx, c0w, r0w, kx4, ky4);
+            } else {
+                // taps from global memory: first tap (+) ixp, (-) nx - ixp - 3, weights as above
+                cpx<R> acc = mk(R(0), R(0));
+                const int cb = sx ? a.nx - ixp - 3 : ixp, rb = sy ? a.ny - iyp - 3 : iyp;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    int r = rb + b;
+                    r = r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r);
+                    cpx<R> racc = mk(R(0), R(0));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int cc = cb + q;
+                        cc = cc < 0 ? cc + a.nx : (cc >= a.nx ? cc - a.nx : cc);
+                        racc = racc + a.spec[(int64_t)r * a.nx + cc] * kx4[q];
+                    }
+                    acc = acc + racc * ky4[b];
+                }
+                v = acc;
+            }
             v = v * ((kx & 1) ? -scale : scale);
             if (in) a.out[(int64_t)ky * a.mx + kx] = v;
         }
@@ -153,9 +275,10 @@ __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
 
 template <typename R>
 hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st) {
-    dim3 block(64, 4);
-    const int nb = (a.nax + 63) / 64;
-    const int nrows = (a.nay + 3) / 4;
+    constexpr int T = kGatherTile;
+    dim3 block(T * T);
+    const int nb = (a.nax + T - 1) / T;
+    const int nrows = (a.nay + T - 1) / T;
     const int per = (nrows + kXcds - 1) / kXcds;
     dim3 grid(nb, kXcds * per);
     hipLaunchKernelGGL(stretch_gather_kernel<R>, grid, block, 0, st, a);
