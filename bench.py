@@ -33,6 +33,114 @@ WORKLOADS = {
 }
 
 
+PROFILE_JSON = os.path.join(ROOT, "profiles", "counters_uwa120_16k.json")
+PROFILE_MD = os.path.join(ROOT, "profiles", "nufds_kernels_uwa120_16k.md")
+OUR_KERNELS = ("fft_pass_kernel", "stretch_gather_kernel", "output_gather_kernel")
+
+
+def source_hash() -> str:
+    """Hash of the kernel and host sources: hardware counters taken on other sources do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2410_13474_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(role):
+    """HBM bytes per launch of a kernel role from the committed counter summary, or None when the
+    summary is missing or was taken on different sources."""
+    try:
+        rec = json.load(open(PROFILE_JSON))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash() or role not in rec.get("roles", {}):
+        return None
+    r = rec["roles"][role]
+    return r["fetch_bytes"] + r["write_bytes"]
+
+
+def summarize_profile(d):
+    """rocprofv3 CSVs -> profiles/counters_uwa120_16k.json and the markdown summary."""
+    import csv
+    import re
+
+    def rows(sub, name):
+        import glob
+        fs = sorted(glob.glob(os.path.join(d, sub, "*" + name)))
+        return list(csv.DictReader(open(fs[0]))) if fs else []
+
+    def short(k):
+        k = re.sub(r"\(.*", "", k).replace("void ", "").replace("nufds::", "")
+        return k.strip()
+
+    roles = json.load(open(os.path.join(d, "roles.json")))["roles"]
+    out = {"source_hash": source_hash(), "workload": "uwa120_16k", "roles": {}, "calibration": {}}
+    counters = {}
+    for sub, cname in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        rs = [r for r in rows(sub, "counter_collection.csv") if r["Counter_Name"] == cname]
+        rs.sort(key=lambda r: int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))))
+        copies = [r for r in rs if "copyBuffer" in r["Kernel_Name"]]
+        gmax = max((int(r["Grid_Size"]) for r in copies), default=0)
+        copy = [float(r["Counter_Value"]) for r in copies if int(r["Grid_Size"]) == gmax]
+        # a 1 GiB device copy reads and writes 1048576 KiB
+        factor = 1048576.0 / (sum(copy) / len(copy)) if copy else 1.0
+        out["calibration"][cname] = {"copy_kib": sum(copy) / len(copy) if copy else None, "factor": factor}
+        ours = [r for r in rs if any(k in r["Kernel_Name"] for k in OUR_KERNELS)]
+        n_steps = len(ours) // len(roles)
+        ours = ours[len(ours) - n_steps * len(roles):]
+        per = {}
+        for i, r in enumerate(ours):
+            per.setdefault(roles[i % len(roles)], []).append(float(r["Counter_Value"]) * 1024 * factor)
+        counters[cname] = {k: sum(v) / len(v) for k, v in per.items()}
+    for role in roles:
+        out["roles"][role] = {"fetch_bytes": counters["FETCH_SIZE"].get(role),
+                              "write_bytes": counters["WRITE_SIZE"].get(role)}
+    stats = rows("trace", "kernel_stats.csv")
+    out["kernel_stats"] = [{"kernel": short(r["Name"]), "calls": int(r["Calls"]),
+                            "avg_ms": float(r["AverageNs"]) / 1e6} for r in stats]
+    meta = json.load(open(os.path.join(d, "roles.json")))
+    out["bench"] = {"ms_per_step": meta.get("ms_per_step"), "avg_ms": meta.get("avg_ms"),
+                    "algorithmic_bytes": meta.get("bytes")}
+    json.dump(out, open(PROFILE_JSON, "w"), indent=1)
+    lines = ["# NU-FDS kernels, 16384^2 120 deg full view (complex64)", "",
+             "Workload: 16384^2 hologram, pitch = lambda / (2 sin 60 deg), lambda = 0.5 um, 1024 points "
+             "(seed 1003), z = 15 mm, full 16384^2 view, FrT size M = 25600.  One MI355X.", "",
+             f"Sources: hash {out['source_hash']} (bench.py's source_hash of paper_2410_13474_amd/csrc); "
+             "bench.py reports `roofline.traffic` only while the sources still match.", "",
+             "Commands (from /tmp with TMPDIR=/tmp; R = repository root, P = an output folder):", "", "```",
+             "rocprofv3 --kernel-trace --stats -d $P/trace -o run --output-format csv -- python3 $R/bench.py "
+             "--steps 5 --warmup 1 --no-cpu --no-serving --copy-calibration --roles-out $P/roles.json",
+             "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 $R/bench.py "
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --copy-calibration",
+             "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 $R/bench.py "
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --copy-calibration",
+             "python3 $R/bench.py --summarize-profile $P", "```", "",
+             "## Kernel statistics (rocprofv3 --stats, complex64 and complex128 steps and plan builds)", "",
+             "| kernel | calls | average ms |", "|---|---|---|"]
+    for k in out["kernel_stats"]:
+        if any(x in k["kernel"] for x in OUR_KERNELS + ("map_table", "synth")):
+            lines.append(f"| `{k['kernel']}` | {k['calls']} | {k['avg_ms']:.3f} |")
+    cal = out["calibration"]
+    lines += ["", "## HBM bytes per launch (complex64 step)", "",
+              f"Calibration: a 1 GiB device copy reads FETCH_SIZE = {cal['FETCH_SIZE']['copy_kib']:.0f} KiB "
+              f"and WRITE_SIZE = {cal['WRITE_SIZE']['copy_kib']:.0f} KiB, so the counters are scaled by "
+              f"{cal['FETCH_SIZE']['factor']:.4f} (fetch) and {cal['WRITE_SIZE']['factor']:.4f} (write).", "",
+              "| role | bench avg ms (HIP events) | algorithmic GB | HBM read GB | HBM written GB | traffic / algorithmic |",
+              "|---|---|---|---|---|---|"]
+    for role, r in out["roles"].items():
+        alg = (meta.get("bytes") or {}).get(role)
+        ms_r = (meta.get("avg_ms") or {}).get(role)
+        tot = (r["fetch_bytes"] or 0) + (r["write_bytes"] or 0)
+        lines.append(f"| {role} | {ms_r:.3f} | {alg / 1e9:.2f} | {r['fetch_bytes'] / 1e9:.2f} | "
+                     f"{r['write_bytes'] / 1e9:.2f} | {tot / alg:.2f} |")
+    open(PROFILE_MD, "w").write("\n".join(lines) + "\n")
+    return out
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -48,6 +156,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (a reference for hardware byte counters)")
     ap.add_argument("--no-serving", action="store_true", help="skip the partial-view latency run")
+    ap.add_argument("--roles-out", default=None,
+                    help="write the kernel roles of one step, in launch order, to this JSON file")
+    ap.add_argument("--summarize-profile", default=None, metavar="DIR",
+                    help="no GPU: turn rocprofv3 output under DIR (trace/, fetch/, write/, roles.json) "
+                         "into the committed summaries under profiles/")
     ap.add_argument("--serving-requests", type=int, default=2000)
     return ap.parse_args()
 
@@ -85,7 +198,7 @@ def kernel_table(launches, steps):
 
 
 def cpu_baseline(torch, N):
-    """The float64 oracle on a bounded sample: the 120 deg geometry at 1024^2 (z scaled by 1/16 so
+    """The float64 oracle on a bounded sample: the 120 deg geometry at 2048^2 (z scaled by 1/8 so
     the aperture-to-distance ratio is that of the 16384^2 workload), 16 points.  The oracle's cost does
     not depend on the hologram's content.  numpy runs it on one thread.  Returns the record and the
     relative L2 error of both GPU paths on the same sample."""
@@ -94,19 +207,19 @@ def cpu_baseline(torch, N):
     import oracle
     import synth
 
-    n, fov = 1024, 120.0
+    n, fov = 2048, 120.0
     scale = n / 16384
     dp = synth.fov_pitch(LAM, fov)
     z = 15e-3 * scale
     pc = synth.draw_points(1003, 16, n, n, dp, LAM, 10e-3 * scale, 20e-3 * scale)
     H = synth.point_hologram(pc, n, n, dp, LAM)
-    log("cpu baseline: oracle on the 1024^2 sample ...")
+    log(f"cpu baseline: oracle on the {n}^2 sample ...")
     t0 = time.perf_counter()
     ref = oracle.reconstruct(H, LAM, dp, z)
     dt = time.perf_counter() - t0
     rec = {"value": n * n / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-           "sample": (f"float64 oracle, full 1024^2 view of a 1024^2 120 deg hologram (16 points) at "
-                      f"z = {z * 1e3:.4f} mm (16384^2 geometry scaled by 1/16), one run of {dt:.1f} s on "
+           "sample": (f"float64 oracle, full {n}^2 view of a {n}^2 120 deg hologram (16 points) at "
+                      f"z = {z * 1e3:.4f} mm (16384^2 geometry scaled by {n}/16384), one run of {dt:.1f} s on "
                       f"{os.cpu_count()} host cores ({platform.processor() or platform.machine()}); "
                       f"numpy uses one thread")}
     errs = {}
@@ -225,6 +338,10 @@ def serving(torch, N, n_requests):
 
 def main():
     args = parse()
+    if args.summarize_profile:
+        rec = summarize_profile(args.summarize_profile)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(this path runs on a single MI355X)", file=sys.stderr)
@@ -275,6 +392,13 @@ def main():
                          "alg_bytes_per_step": alg_bytes, "frac_hbm_end_to_end": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "info": {k: plan.info[k] for k in ("mx", "my", "kcx", "kcy", "workspace_bytes", "map_bytes")}}
         outs[prec] = out
+        if args.roles_out and prec == "c64":
+            per_step = len(launches) // args.steps
+            with open(args.roles_out, "w") as f:
+                json.dump({"roles": [name for name, _, _ in launches[:per_step]],
+                           "bytes": {k: v["bytes"] for k, v in kt.items()},
+                           "avg_ms": {k: v["avg_ms"] for k, v in kt.items()},
+                           "ms_per_step": ms}, f)
         del plan
     rel_fp32_fp64 = None
     if "c128" in outs:
@@ -289,7 +413,7 @@ def main():
     dom = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches_per_step"])
     d = kt[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
 
     serve = None
