@@ -132,7 +132,9 @@ constexpr int kGatherWinY = 24;  // window rows at most
 
 template <typename R>
 __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
-    constexpr int T = kGatherTile, WXM = kGatherWinX, WYM = kGatherWinY, CAP = WXM * WYM;
+    constexpr int T = kGatherTile, WXM = kGatherWinX, WYM = kGatherWinY;
+    // complex128 windows are held compactly in at most 512 samples (tiles measure <= 21 x 21)
+    constexpr int CAP = sizeof(R) == 4 ? WXM * WYM : 512;
     constexpr int RG = 256 / WXM;             // row groups of the fill
     constexpr int K = (WYM + RG - 1) / RG;    // fill loads per thread and mirror
     __shared__ cpx<R> win[4][CAP];
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
     const int mnx = r0, mxx = -r1, mny = r2, mxy = -r3;
     // windows: x from mnx (mirror +) or nx - mxx - 3 (mirror -), wx columns; likewise y
     const int wx = mxx - mnx + 4, wy = mxy - mny + 4;
-    const bool fits = any && wx <= WXM && wy <= WYM;
+    const bool fits = any && wx <= WXM && wy <= WYM && wx * wy <= CAP;
     if (fits) {
         const int c = tid % WXM, rg = tid / WXM;
         const bool cin = c < wx;
