@@ -162,6 +162,7 @@ def parse():
                     help="no GPU: turn rocprofv3 output under DIR (trace/, fetch/, write/, roles.json) "
                          "into the committed summaries under profiles/")
     ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-inflight", type=int, default=4, help="server workspaces (streams)")
     return ap.parse_args()
 
 
@@ -244,7 +245,7 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def serving(torch, N, n_requests):
+def serving(torch, N, n_requests, inflight=4):
     """Partial views of one cached 8192^2 120 deg hologram (2048 points, z ~ U[5, 15] mm): square
     views of side S ~ U{512, 1024, 2048, 4096} at pitch Delta_F, centres uniform over the image,
     reconstruction distance z ~ U[5, 15] mm, seed 2004.  First the closed-loop capacity (8 requests
@@ -275,7 +276,7 @@ def serving(torch, N, n_requests):
         gv = N.plan_geometry(LAM, dp, n, n, z, view=v)
         max_m = max(max_m, gv["mx"], gv["my"])
         reqs.append((z, v))
-    srv = N.Server("c64", max_frt_size=max_m, max_view_size=4096, max_inflight=4)
+    srv = N.Server("c64", max_frt_size=max_m, max_view_size=4096, max_inflight=inflight)
     ring = 32
     outs = [torch.empty((4096, 4096), dtype=torch.complex64, device="cuda") for _ in range(ring)]
     pending = [None] * ring
@@ -330,7 +331,7 @@ def serving(torch, N, n_requests):
     return {"p50": p50, "p99": p99, "requests": len(reqs), "load": 0.7, "rate_per_s": rate,
             "capacity_per_s": capacity, "closed_loop_mpix_s": pix / t_closed / 1e6,
             "closed_loop_p50": percentile(lat_c, 0.5), "closed_loop_p99": percentile(lat_c, 0.99),
-            "max_frt_size": max_m, "inflight": 4,
+            "max_frt_size": max_m, "inflight": inflight,
             "workload": "8192^2 120 deg hologram (2048 points), spectrum cached; square views S in "
                         "{512,1024,2048,4096} at Delta_F, uniform centres, z ~ U[5,15] mm, seed 2004; "
                         "Poisson arrivals at 70% of closed-loop capacity"}
@@ -418,7 +419,7 @@ def main():
 
     serve = None
     if not args.no_serving:
-        serve = serving(torch, N, args.serving_requests)
+        serve = serving(torch, N, args.serving_requests, args.serving_inflight)
 
     cpu = None
     errs = {}

@@ -201,7 +201,50 @@ __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
     // windows: x from mnx (mirror +) or nx - mxx - 3 (mirror -), wx columns; likewise y
     const int wx = mxx - mnx + 4, wy = mxy - mny + 4;
     const bool fits = any && wx <= WXM && wy <= WYM && wx * wy <= CAP;
-    if (fits) {
+    if (fits && sizeof(R) == 4) {
+        // complex64: each lane copies two adjacent samples of a window row with one 16-byte load
+        // (16 lanes per row, 16 rows per pass); a pair that would run off the spectrum's last
+        // column takes its second sample from column 0 (periodic wrap)
+        constexpr int PX = WXM / 2, PR = 256 / PX, KP = (WYM + PR - 1) / PR;
+        typedef R pair_t __attribute__((ext_vector_type(4), aligned(8)));
+        const int c = 2 * (tid % PX), rg = tid / PX;
+        const bool cin = c < wx;
+        pair_t tmp[4][KP];
+        int gcs[4], grs[4][KP];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int sx = m & 1, sy = m >> 1;
+            const int x0 = sx ? a.nx - mxx - 3 : mnx, y0 = sy ? a.ny - mxy - 3 : mny;
+            int gc = x0 + (cin ? c : 0);
+            gc = gc < 0 ? gc + a.nx : (gc >= a.nx ? gc - a.nx : gc);
+            gcs[m] = gc;
+            const int gcl = gc == a.nx - 1 ? a.nx - 2 : gc;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const int r = rg + k * PR;
+                int gr = y0 + (r < wy ? r : 0);  // branch-free: every thread loads in bounds
+                gr = gr < 0 ? gr + a.ny : (gr >= a.ny ? gr - a.ny : gr);
+                grs[m][k] = gr;
+                tmp[m][k] = *reinterpret_cast<const pair_t*>(a.spec + (int64_t)gr * a.nx + gcl);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const int r = rg + k * PR;
+                if (cin && r < wy) {
+                    cpx<R> s0 = mk(R(tmp[m][k].x), R(tmp[m][k].y)), s1 = mk(R(tmp[m][k].z), R(tmp[m][k].w));
+                    if (gcs[m] == a.nx - 1) {  // rare: the window crosses the last column
+                        s0 = s1;
+                        s1 = a.spec[(int64_t)grs[m][k] * a.nx];
+                    }
+                    win[m][r * wx + c] = s0;
+                    if (c + 1 < wx) win[m][r * wx + c + 1] = s1;
+                }
+            }
+        __syncthreads();
+    } else if (fits) {
         const int c = tid % WXM, rg = tid / WXM;
         const bool cin = c < wx;
         cpx<R> tmp[4][K];
