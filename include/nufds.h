@@ -91,6 +91,8 @@ typedef struct {
     uint64_t map_bytes;       /* of which the stretch-map table */
     int32_t precision;       /* nufds_precision_t */
     uint32_t flags;
+    int32_t fcx0, fcxn;      /* FrT columns the view reads (first, count): the y transform runs on
+                                these only */
 } nufds_plan_info_t;
 
 /*
@@ -163,7 +165,8 @@ nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_
  * nufds_debug_copy -- copy an internal buffer of the last execute (tests).
  *
  * which: 1 = hologram spectrum (step 2 FFT, [ny][nx]),
- *        2 = pre-chirp FrT F ([my][mx], F[m] at x' = K_c D_F + (m - M/2) D_F),
+ *        2 = pre-chirp FrT F ([my][mx], F[m] at x' = K_c D_F + (m - M/2) D_F; only columns
+ *            fcx0 .. fcx0 + fcxn - 1 of nufds_plan_info hold F, the others the x transform alone),
  *        3 = stretch-map table (float64 pairs, see nufds_plan_info map_bytes).
  * d_dst: device buffer of at least *bytes; if d_dst is NULL only *bytes is
  * set.  Enqueued on stream.  Errors: INVALID_ARG.

@@ -158,6 +158,17 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
     out->padx = padx;
     out->pady = pady;
     out->flags = flags;
+    // FrT columns the view reads: the taps of x' over the window (plus two samples of margin for the
+    // GPU's own evaluation of the map), from a 16-column boundary; the y transform runs on these only
+    if (mx > 0) {
+        const double q0 = xl / dfx - kcx + mx / 2, q1 = xh / dfx - kcx + mx / 2;
+        long c0 = (long)std::floor(q0) - 3, c1 = (long)std::floor(q1) + 4;
+        c0 = std::max(0L, c0) / 16 * 16;
+        c1 = std::min((long)mx - 1, c1);
+        if (c1 < c0) c1 = c0;
+        out->fcx0 = (int32_t)c0;
+        out->fcxn = (int32_t)(c1 - c0 + 1);
+    }
     if (mx <= 0 || my <= 0) return fail(NUFDS_ERR_UNSUPPORTED, "FrT size out of range");
     return NUFDS_OK;
 }
@@ -624,14 +635,17 @@ nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_
         res = w1;
     }
     // and along y
-    if (!build_axis(1, my, mx, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
+    // only the columns the output gather reads (fcx0 .. fcx0 + fcxn - 1) need the y transform
+    if (!build_axis(1, my, g.fcxn, mx, +1, 1, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "FrT column length");
+    const size_t coff = (size_t)g.fcx0 * sizeof(cpx<R>);
+    auto col = [coff](void* b) { return static_cast<void*>(static_cast<char*>(b) + coff); };
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], res, res, 0, 1, 1, R(1), cyv, s));
+        NUFDS_TRY(run_pass<R>(p, "yop", ap.passes[0], col(res), col(res), 0, 1, 1, R(1), cyv, s));
     } else {
         void* oth = (res == w1) ? w2 : w1;
-        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], res, oth, 0, 1, 0, R(1), nullptr, s));
-        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], oth, res, 0, 0, 0, R(1), cyv, s));
-        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], res, oth, 0, 0, 1, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "yop_a", ap.passes[0], col(res), col(oth), 0, 1, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "yop_ba", ap.passes[1], col(oth), col(res), 0, 0, 0, R(1), cyv, s));
+        NUFDS_TRY(run_pass<R>(p, "yop_b", ap.passes[2], col(res), col(oth), 0, 0, 1, R(1), nullptr, s));
         res = oth;
     }
     p->result = res;
@@ -677,7 +691,7 @@ nufds_status_t prepare_twiddles(nufds_plan* p, bool fft1, bool band) {
     // every transform must have a pass plan; create the twiddle tables its passes read, so that
     // execute only enqueues kernels
     const int axes[4][5] = {{0, g.nx, g.ny, g.nx, 0}, {1, g.ny, g.nx, g.nx, 0}, {0, g.mx, g.my, g.mx, 1},
-                            {1, g.my, g.mx, g.mx, 1}};
+                            {1, g.my, g.fcxn, g.mx, 1}};
     for (int i = fft1 ? 0 : 2; i < (band ? 4 : 2); ++i) {
         const auto& a = axes[i];
         AxisPlan ap;

@@ -47,7 +47,8 @@ class PlanInfo(ctypes.Structure):
                 ("image_size", ctypes.c_double), ("xlo", ctypes.c_double), ("xhi", ctypes.c_double),
                 ("ylo", ctypes.c_double), ("yhi", ctypes.c_double), ("padx", ctypes.c_double),
                 ("pady", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64), ("map_bytes", ctypes.c_uint64),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fcx0", ctypes.c_int32),
+                ("fcxn", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
