@@ -185,10 +185,19 @@ struct Composite {
 
     template <int N2, int K1>
     __device__ __forceinline__ static void twiddle(cpx<R>* v, int sign) {
-        if constexpr (N2 * K1 != 0) {
+        constexpr int M = (N2 * K1) % RAD;
+        cpx<R>& x = v[N2 + B * K1];
+        if constexpr (M == 0) {
+        } else if constexpr (4 * M == RAD) {          // exp(sign i pi / 2) = sign i
+            x = sign < 0 ? mul_mi(x) : mul_pi(x);
+        } else if constexpr (2 * M == RAD) {          // -1
+            x = mk(-x.x, -x.y);
+        } else if constexpr (4 * M == 3 * RAD) {      // -sign i
+            x = sign < 0 ? mul_pi(x) : mul_mi(x);
+        } else {
             const R c = R(TwC<N2 * K1, RAD>::c);
             const R s = R(TwC<N2 * K1, RAD>::s) * R(sign);
-            v[N2 + B * K1] = v[N2 + B * K1] * mk(c, s);
+            x = x * mk(c, s);
         }
     }
     template <int N2>
@@ -268,7 +277,8 @@ __device__ __forceinline__ void apply_twiddles(cpx<R>* v, cpx<R> w) {
 #pragma unroll
         for (int t = 1; t < RAD; ++t) {
             if (t % 4 == 0) hi = (t == 4) ? w4 : hi * w4;
-            v[t] = v[t] * ((t % 4) ? hi * lo[t % 4] : hi);
+            // below t = 4 hi is 1: no product with it (x * 0 does not fold in IEEE arithmetic)
+            v[t] = v[t] * (t < 4 ? lo[t] : ((t % 4) ? hi * lo[t % 4] : hi));
         }
     }
 }
@@ -420,11 +430,12 @@ struct StageNb {
 // order that makes their global accesses contiguous (j fastest for transforms that run along memory,
 // w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
 // precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
-template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN>
+template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN>
 __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
                                           const StorePlain<R>& st, const ChainMul<R>& ch,
                                           const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
-                                          int sign, int tid, int T) {
+                                          int tid, int T) {
+    constexpr int sign = SGN;  // transform direction, a compile-time constant of the stage
     constexpr int NB = StageNb<RAD, MAXE, NBMAX>::value;
     constexpr uint32_t ES = sizeof(cpx<R>);
     // per-stage opaque copy of the thread index: keeps the compiler from hoisting every
@@ -568,14 +579,14 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     if (!LAST) __syncthreads();
 }
 
-template <typename R, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN>
+template <typename R, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN>
 __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m,
                                             const LoadPlain<R>& ld, const StorePlain<R>& st, const ChainMul<R>& ch,
                                             const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
-                                            int sign, int tid, int T) {
+                                            int tid, int T) {
 #define NUFDS_STAGE(RR)                                                                             \
     if constexpr ((RR) <= MAXE)                                                                     \
-        fft_stage<R, RR, MAXE, NBMAX, PAD, FIRST, LAST, CHAIN>(lds, d, m, ld, st, ch, tw, twf, Ns, sign, tid, T)
+        fft_stage<R, RR, MAXE, NBMAX, PAD, FIRST, LAST, CHAIN, SGN>(lds, d, m, ld, st, ch, tw, twf, Ns, tid, T)
     switch (r) {
         case 16: NUFDS_STAGE(16); break;
         case 8: NUFDS_STAGE(8); break;
@@ -594,7 +605,7 @@ __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& 
 
 // NBMAX: butterflies a thread holds per stage.  NBMAX = 1 is the small-tile variant (one butterfly
 // per thread, more threads, fewer live registers); the other variant serves long single-pass rows.
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
                                                         const cpx<R>* __restrict__ tw,
                                                         const cpx<R>* __restrict__ twf,
@@ -626,8 +637,7 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     // transform 1: stage 0 reads global memory; the last stage writes global memory, or, in a chain
     // pass, multiplies by the chain vector (the chirp of Eq. 2) on its way to LDS
     int Ns = 1;
-    const int sg = d.sign;
-#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, PAD, F, L, C>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg, tid, T)
+#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, PAD, F, L, C, SGN>(r, lds, d, m, ld, st, ch, tw, twf, Ns, tid, T)
     if constexpr (!CHAINP) {
         for (int s = 0; s < nst; ++s) {
             const int r = d.rad[s];
@@ -651,24 +661,23 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     }
 #undef NUFDS_RUN
     // transform 2 (opposite sign): from LDS, the last stage to global memory
-    const int sg2 = -d.sign;
     Ns = 1;
     for (int s = 0; s < nst; ++s) {
         const int r = d.rad[s];
         if (s == nst - 1)
-            fft_stage_r<R, MAXE, NBMAX, PAD, false, true, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+            fft_stage_r<R, MAXE, NBMAX, PAD, false, true, false, -SGN>(r, lds, d, m, ld, st, ch, tw, twf, Ns, tid, T);
         else
-            fft_stage_r<R, MAXE, NBMAX, PAD, false, false, false>(r, lds, d, m, ld, st, ch, tw, twf, Ns, sg2, tid, T);
+            fft_stage_r<R, MAXE, NBMAX, PAD, false, false, false, -SGN>(r, lds, d, m, ld, st, ch, tw, twf, Ns, tid, T);
         Ns *= r;
     }
     }
 }
 
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN>
 static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                                  const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     static bool attr_set = false;
-    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD>;
+    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD, SGN>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -682,25 +691,34 @@ static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, cons
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
-                       const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
+template <typename R, int SG>
+static hipError_t launch_signed(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                                const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     constexpr int OE = OneBflyElems<R>::value, OT = OneBflyThreads<R>::value, ME = MaxElems<R>::value;
     // tiles of 8 or more columns keep their lanes on consecutive LDS words without padding; the
     // several-butterflies variant serves long rows (narrow tiles) only
     const bool pad = d.W < 8;
     if (d.chain) {
         if (d.one_bfly) {
-            if (pad) return launch_variant<R, OE, 1, OT, true, true>(d, ld, st, tw, twf, chainvec, s);
-            return launch_variant<R, OE, 1, OT, true, false>(d, ld, st, tw, twf, chainvec, s);
+            if (pad) return launch_variant<R, OE, 1, OT, true, true, SG>(d, ld, st, tw, twf, chainvec, s);
+            return launch_variant<R, OE, 1, OT, true, false, SG>(d, ld, st, tw, twf, chainvec, s);
         }
-        return launch_variant<R, ME, 64, 1024, true, true>(d, ld, st, tw, twf, chainvec, s);
+        return launch_variant<R, ME, 64, 1024, true, true, SG>(d, ld, st, tw, twf, chainvec, s);
     }
     if (d.one_bfly) {
-        if (pad) return launch_variant<R, OE, 1, OT, false, true>(d, ld, st, tw, twf, chainvec, s);
-        return launch_variant<R, OE, 1, OT, false, false>(d, ld, st, tw, twf, chainvec, s);
+        if (pad) return launch_variant<R, OE, 1, OT, false, true, SG>(d, ld, st, tw, twf, chainvec, s);
+        return launch_variant<R, OE, 1, OT, false, false, SG>(d, ld, st, tw, twf, chainvec, s);
     }
-    return launch_variant<R, ME, 64, 1024, false, true>(d, ld, st, tw, twf, chainvec, s);
+    return launch_variant<R, ME, 64, 1024, false, true, SG>(d, ld, st, tw, twf, chainvec, s);
+}
+
+
+// The transform direction is a template parameter of the kernel (the sign folds into the butterflies).
+template <typename R>
+hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                       const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
+    if (d.sign < 0) return launch_signed<R, -1>(d, ld, st, tw, twf, chainvec, s);
+    return launch_signed<R, 1>(d, ld, st, tw, twf, chainvec, s);
 }
 
 template hipError_t launch_pass<float>(const PassDesc&, const LoadPlain<float>&,
