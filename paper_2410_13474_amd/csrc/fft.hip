@@ -430,7 +430,8 @@ struct StageNb {
 // order that makes their global accesses contiguous (j fastest for transforms that run along memory,
 // w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
 // precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
-template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN>
+template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN, int LC = 0,
+          int NSC = 0, int WLOG = -1>
 __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
                                           const StorePlain<R>& st, const ChainMul<R>& ch,
                                           const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
@@ -447,7 +448,10 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     int ib_s = __builtin_amdgcn_readfirstlane(m.ib), ob_s = __builtin_amdgcn_readfirstlane(m.ob);
     int L = __builtin_amdgcn_readfirstlane(d.L);
     asm volatile("" : "+s"(ib_s), "+s"(ob_s), "+s"(L));
-    const int lw = d.logW, W = 1 << lw;
+    // kernels specialised for one radix plan know the length, the stride and the tile width
+    if constexpr (LC > 0) L = LC;
+    if constexpr (NSC > 0) Ns = NSC;
+    const int lw = WLOG >= 0 ? WLOG : d.logW, W = 1 << lw;
     const int LR = L / RAD;
     const int B = LR << lw;
     // the first stage has Ns = 1 (q = j, k = 0), the last Ns = L / RAD (q = 0, k = j)
@@ -673,6 +677,107 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     }
 }
 
+// The stages of one transform with its radix plan known at compile time (Ns, the length and the
+// tile width become constants).  G_IN: the first stage reads global memory; G_OUT: the last stage
+// writes global memory; CH: the last stage applies the chain vector on its way to LDS.
+template <typename R, int MAXE, int NBMAX, bool PAD, bool G_IN, bool G_OUT, bool CH, int SGN, int LC, int WLOG,
+          int NS, int R0, int... RS>
+__device__ __forceinline__ void fixed_stages(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
+                                             const StorePlain<R>& st, const ChainMul<R>& ch,
+                                             const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int tid,
+                                             int T) {
+    constexpr bool last = sizeof...(RS) == 0;
+    fft_stage<R, R0, MAXE, NBMAX, PAD, G_IN && NS == 1, last && G_OUT, last && CH, SGN, LC, NS, WLOG>(
+        lds, d, m, ld, st, ch, tw, twf, NS, tid, T);
+    if constexpr (!last)
+        fixed_stages<R, MAXE, NBMAX, PAD, G_IN, G_OUT, CH, SGN, LC, WLOG, NS * R0, RS...>(lds, d, m, ld, st, ch, tw,
+                                                                                         twf, tid, T);
+}
+
+// fft_pass_kernel for one radix plan (RADS, product LC) and tile width 2^WLOG.
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN, int WLOG, int... RADS>
+__global__ void __launch_bounds__(MAXT) fft_fixed_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
+                                                         const cpx<R>* __restrict__ tw,
+                                                         const cpx<R>* __restrict__ twf,
+                                                         const cpx<R>* __restrict__ chainvec) {
+    constexpr int LC = (RADS * ...);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x, T = blockDim.x;
+    int ta = blockIdx.y, tb = blockIdx.x;
+    if (d.xcd_rows) {
+        const int nb = gridDim.x, na = d.tiles_a;
+        const int lin = blockIdx.y * nb + blockIdx.x;
+        const int xcd = lin % kXcds, slot = lin / kXcds;
+        const int per = (na + kXcds - 1) / kXcds;
+        const int row = xcd * per + slot / nb;
+        if (row >= na) return;
+        ta = row;
+        tb = slot % nb;
+    }
+    const TileMap m = tile_map(d, ta, tb);
+    const ChainMul<R> ch{chainvec};
+    if constexpr (!CHAINP) {
+        fixed_stages<R, MAXE, NBMAX, PAD, true, true, false, SGN, LC, WLOG, 1, RADS...>(lds, d, m, ld, st, ch, tw, twf,
+                                                                                      tid, T);
+    } else {
+        fixed_stages<R, MAXE, NBMAX, PAD, true, false, true, SGN, LC, WLOG, 1, RADS...>(lds, d, m, ld, st, ch, tw, twf,
+                                                                                      tid, T);
+        fixed_stages<R, MAXE, NBMAX, PAD, false, true, false, -SGN, LC, WLOG, 1, RADS...>(lds, d, m, ld, st, ch, tw,
+                                                                                        twf, tid, T);
+    }
+}
+
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN, int WLOG, int... RADS>
+static hipError_t launch_fixed(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                               const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
+    static bool attr_set = false;
+    auto kern = &fft_fixed_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD, SGN, WLOG, RADS...>;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const size_t shm = (size_t)lds_elems(d.L * d.W) * sizeof(cpx<R>);
+    const int ga = d.xcd_rows ? kXcds * ((d.tiles_a + kXcds - 1) / kXcds) : d.tiles_a;
+    dim3 grid(d.tiles_b, ga), block(d.nthreads);
+    hipLaunchKernelGGL(kern, grid, block, shm, s, d, ld, st, tw, twf, chainvec);
+    return hipGetLastError();
+}
+
+// Radix plans with a specialised kernel: the transforms of the common sizes (lengths 128 and 160,
+// the halves of 16384 and 25600, over tiles of 8-32 columns; 16384 in one pass).
+template <typename R, int SG>
+static bool launch_specialised(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
+                               const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s, hipError_t* err) {
+    constexpr int OE = OneBflyElems<R>::value, OT = OneBflyThreads<R>::value, ME = MaxElems<R>::value;
+    auto is = [&](int L, int W, int n, int r0, int r1, int r2, int r3) {
+        return d.L == L && d.W == W && d.nst == n && d.rad[0] == r0 && d.rad[1] == r1 && (n < 3 || d.rad[2] == r2) &&
+               (n < 4 || d.rad[3] == r3);
+    };
+#define NUFDS_FIX2(LL, WW, WL, A, B)                                                                            \
+    if (d.one_bfly && is(LL, WW, 2, A, B, 0, 0)) {                                                              \
+        *err = d.chain ? launch_fixed<R, OE, 1, OT, true, (WW < 8), SG, WL, A, B>(d, ld, st, tw, twf, chainvec, s)  \
+                       : launch_fixed<R, OE, 1, OT, false, (WW < 8), SG, WL, A, B>(d, ld, st, tw, twf, chainvec, s); \
+        return true;                                                                                            \
+    }
+    NUFDS_FIX2(160, 32, 5, 16, 10)
+    NUFDS_FIX2(160, 16, 4, 16, 10)
+    NUFDS_FIX2(160, 8, 3, 16, 10)
+    NUFDS_FIX2(128, 32, 5, 16, 8)
+    NUFDS_FIX2(128, 16, 4, 16, 8)
+    NUFDS_FIX2(128, 8, 3, 16, 8)
+#undef NUFDS_FIX2
+    if constexpr (sizeof(R) == 4) {  // complex64 only: 16384 elements fit one tile
+        if (!d.one_bfly && !d.chain && is(16384, 1, 4, 16, 16, 16, 4)) {
+            *err = launch_fixed<R, ME, 64, 1024, false, true, SG, 0, 16, 16, 16, 4>(d, ld, st, tw, twf, chainvec, s);
+            return true;
+        }
+    }
+    return false;
+}
+
 template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN>
 static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                                  const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
@@ -717,7 +822,12 @@ static hipError_t launch_signed(const PassDesc& d, const LoadPlain<R>& ld, const
 template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                        const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
-    if (d.sign < 0) return launch_signed<R, -1>(d, ld, st, tw, twf, chainvec, s);
+    hipError_t e = hipSuccess;
+    if (d.sign < 0) {
+        if (launch_specialised<R, -1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
+        return launch_signed<R, -1>(d, ld, st, tw, twf, chainvec, s);
+    }
+    if (launch_specialised<R, 1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
     return launch_signed<R, 1>(d, ld, st, tw, twf, chainvec, s);
 }
 
