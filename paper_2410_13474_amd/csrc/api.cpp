@@ -559,6 +559,13 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* 
     a.table = static_cast<const double*>(p->table.p);
     a.kxt = p->kxt;
     a.kyt = p->kyt;
+    a.bounds = nullptr;
+    a.tbx = a.tby = 0;
+    if (p->table.p) {
+        a.bounds = reinterpret_cast<const int4*>(static_cast<const char*>(p->table.p) + map_entries_bytes(p->kxt, p->kyt));
+        a.tbx = map_tiles_x(p->kxt);
+        a.tby = map_tiles_y(p->kyt);
+    }
     a.nx = g.nx;
     a.ny = g.ny;
     a.mx = g.mx;
@@ -572,6 +579,10 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* 
     abs_range(a.gy0, a.gy0 + g.my - 1, &lo, &hi);
     a.ay0 = lo;
     a.nay = hi - lo + 1;
+    a.tx0 = a.ax0 / kGatherTile;
+    a.ty0 = a.ay0 / kGatherTile;
+    a.ntx = (a.ax0 + a.nax - 1) / kGatherTile - a.tx0 + 1;
+    a.nty = (a.ay0 + a.nay - 1) / kGatherTile - a.ty0 + 1;
     a.nostretch = (p->flags & NUFDS_FLAG_NO_STRETCH) ? 1 : 0;
     const uint64_t es = sizeof(cpx<R>);
     const uint64_t mm = (uint64_t)g.mx * g.my, nn = (uint64_t)g.nx * g.ny;
@@ -772,8 +783,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
         const int by = std::max(std::abs(g.kcy - g.my / 2), std::abs(g.kcy + g.my / 2 - 1));
         p->kxt = std::min(bx, kmx);
         p->kyt = std::min(by, kmy);
-        const size_t entries = (size_t)(p->kxt + 1) * (p->kyt + 1);
-        if ((st = dev_alloc(p->table, entries * 2 * sizeof(double))) != NUFDS_OK) return bail(st);
+        if ((st = dev_alloc(p->table, map_table_bytes(p->kxt, p->kyt))) != NUFDS_OK) return bail(st);
         he = launch_map_table(static_cast<double*>(p->table.p), p->kxt, p->kyt, wavelength, nx * pitch, ny * pitch, s,
                               nullptr);
         if (he != hipSuccess) return bail(hip_fail(he, "map table launch"));
@@ -889,7 +899,7 @@ nufds_status_t nufds_debug_copy(nufds_plan_t plan, int32_t which, void* d_dst, u
     switch (which) {
         case 1: src = plan->spec.p; n = (uint64_t)plan->info.nx * plan->info.ny * plan->esize; break;
         case 2: src = plan->result; n = (uint64_t)plan->info.mx * plan->info.my * plan->esize; break;
-        case 3: src = plan->table.p; n = plan->table.bytes; break;
+        case 3: src = plan->table.p; n = plan->table.p ? map_entries_bytes(plan->kxt, plan->kyt) : 0; break;
         default: return fail(NUFDS_ERR_INVALID_ARG, "unknown buffer");
     }
     *bytes = n;

@@ -30,11 +30,18 @@ __global__ void map_table_kernel(double* __restrict__ table, int kxt, int kyt, d
     table[2 * e + 1] = py;
 }
 
+__global__ void tile_bounds_kernel(const double* __restrict__ table, int kxt, int kyt, int4* __restrict__ bounds);
+
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
                             double s, hipStream_t st) {
     dim3 block(64, 4);
     dim3 grid((kxt + 1 + 63) / 64, (kyt + 1 + 3) / 4);
     hipLaunchKernelGGL(map_table_kernel, grid, block, 0, st, table, kxt, kyt, wavelength, npx, npy, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int4* bounds = reinterpret_cast<int4*>(reinterpret_cast<char*>(table) + map_entries_bytes(kxt, kyt));
+    hipLaunchKernelGGL(tile_bounds_kernel, dim3(map_tiles_x(kxt), map_tiles_y(kyt)), dim3(kGatherTile * kGatherTile), 0,
+                       st, table, kxt, kyt, bounds);
     return hipGetLastError();
 }
 
@@ -105,159 +112,193 @@ __device__ __forceinline__ cpx<R> keys_spectrum(const cpx<R>* __restrict__ spec,
 // k_g = K_c + k' - M/2) is the hologram spectrum Keys-interpolated at the pre-image of k_g.  The map
 // is odd in each axis, so the pre-image of (+-|k_gx|, +-|k_gy|) is (+-P_x, +-P_y) from one table entry.
 // Output carries the (-1)^(k'_x) centring sign of the inverse transform that follows.
-// Keys 4 x 4 from a window of the spectrum held in LDS ([rows][wx]; taps at r0..r0+3, c0..c0+3).
-template <typename R>
-__device__ __forceinline__ cpx<R> keys_window(const cpx<R>* w, int wx, int c0, int r0, const R* kx, const R* ky) {
-    cpx<R> acc = mk(R(0), R(0));
+
+// Window bounds of one 16 x 16 tile of table entries (layout in kernels.h); one workgroup per tile.
+__global__ void __launch_bounds__(256) tile_bounds_kernel(const double* __restrict__ table, int kxt, int kyt,
+                                                          int4* __restrict__ bounds) {
+    constexpr int T = kGatherTile;
+    __shared__ int red[4][4];
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x * T + tid % T, ky = blockIdx.y * T + tid / T;
+    bool valid = kx <= kxt && ky <= kyt;
+    const int64_t e = valid ? (int64_t)ky * (kxt + 1) + kx : 0;
+    const double px = table[2 * e], py = table[2 * e + 1];
+    valid = valid && px == px;
+    const int fx = valid ? (int)floor(px) - 1 : 0, fy = valid ? (int)floor(py) - 1 : 0;
+    int r[4] = {valid ? fx : INT_MAX, valid ? -fx : INT_MAX, valid ? fy : INT_MAX, valid ? -fy : INT_MAX};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const cpx<R>* row = w + (r0 + b) * wx + c0;
-        const cpx<R> racc = row[0] * kx[0] + row[1] * kx[1] + row[2] * kx[2] + row[3] * kx[3];
-        acc = acc + racc * ky[b];
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = min(r[i], __shfl_xor(r[i], o));
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[tid >> 6][i] = r[i];
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = min(min(red[0][i], red[1][i]), min(red[2][i], red[3][i]));
+        int4 b;
+        b.x = r[0];
+        b.y = r[0] == INT_MAX ? INT_MAX : -r[1];
+        b.z = r[0] == INT_MAX ? INT_MAX : r[2];
+        b.w = r[0] == INT_MAX ? INT_MAX : -r[3];
+        bounds[blockIdx.y * gridDim.x + blockIdx.x] = b;
     }
-    return acc;
 }
 
-// One workgroup covers a 16 x 16 tile of quadrant entries.  The pre-images of a tile lie within about
-// 20 x 20 spectral samples (the inverse stretch contracts), so the workgroup first copies the four
-// mirrored spectrum windows under its stencils into LDS with plain row loads and then interpolates
-// from LDS: each spectrum sample is fetched once per tile instead of once per tap, which relieves the
-// texture-address unit that bounds a per-tap gather.  The Keys kernel is even, so the mirror -p uses
-// the weights of p in reverse order on the taps floor(-p) - 1 .. floor(-p) + 2 reflected, i.e. from
-// N - (first tap of p) - 3 on; one set of weights per axis serves all four mirrors.  A tile whose
-// window would not fit (none at the sizes measured) interpolates straight from global memory.
-constexpr int kGatherTile = 16;
-constexpr int kGatherWinX = 32;  // window columns at most (one per lane of half a wave)
-constexpr int kGatherWinY = 24;  // window rows at most
+// Global accesses as a wave-uniform base (scalar registers) plus a 32-bit per-lane byte offset.
+typedef __attribute__((address_space(1))) char gbyte;
+template <typename T>
+__device__ __forceinline__ gbyte* uniform_ptr(const T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gbyte*)(((uint64_t)hi << 32) | lo);
+}
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(8)));  // two complex64 samples
+typedef double d2_t __attribute__((ext_vector_type(2)));              // one complex128 sample
+template <typename R> struct Load16 { typedef f4u_t type; };
+template <> struct Load16<double> { typedef d2_t type; };
+template <typename V>
+__device__ __forceinline__ V load16(gbyte* base, uint32_t off) {
+    return *reinterpret_cast<const V __attribute__((address_space(1)))*>(base + off);
+}
+template <typename R>
+__device__ __forceinline__ void store_cpx(gbyte* base, uint32_t off, cpx<R> v) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *reinterpret_cast<v2 __attribute__((address_space(1)))*>(base + off) = w;
+}
 
+// Window of one mirror in LDS: rows of a fixed pitch P (odd, so that rows start on different banks),
+// at most kGatherRows rows.  A 16 x 16 tile's windows measure at most 21 x 21 samples (the inverse
+// stretch contracts, so neighbouring entries' pre-images are at most a sample apart along the tile,
+// plus the drift across it and the 4-tap stencil).
+template <typename R> struct GatherPitch { static constexpr int value = 25; };
+template <> struct GatherPitch<double> { static constexpr int value = 21; };
+constexpr int kGatherRows = 24;
+
+// One workgroup covers a 16 x 16 tile of quadrant entries.  The window bounds of the tile come from
+// the table (computed once per table), so the workgroup starts copying the four mirrored spectrum
+// windows under its stencils into LDS at once, alongside its entries' own table loads, and then
+// interpolates from LDS: each spectrum sample is fetched once per tile instead of once per tap.  The
+// Keys kernel is even, so the mirror -p uses the weights of p in reverse order on the taps
+// floor(-p) - 1 .. floor(-p) + 2 reflected, i.e. from N - (first tap of p) - 3 on; one set of 16
+// weight products serves all four mirrors, with the centring sign (equal for both x mirrors, whose
+// k'_x differ by 2 |k_gx|) and the mask folded in.  A window that crosses the spectrum's edge is
+// copied with periodic indices; one that would not fit LDS (none at the sizes measured) is
+// interpolated straight from global memory.
 template <typename R>
 __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
-    constexpr int T = kGatherTile, WXM = kGatherWinX, WYM = kGatherWinY;
-    // complex128 windows are held compactly in at most 512 samples (tiles measure <= 21 x 21)
-    constexpr int CAP = sizeof(R) == 4 ? WXM * WYM : 512;
-    constexpr int RG = 256 / WXM;             // row groups of the fill
-    constexpr int K = (WYM + RG - 1) / RG;    // fill loads per thread and mirror
-    __shared__ cpx<R> win[4][CAP];
-    __shared__ int red[4][4];
+    constexpr int T = kGatherTile, P = GatherPitch<R>::value, WY = kGatherRows, CAP = P * WY;
+    constexpr int ES = sizeof(cpx<R>);
+    __shared__ cpx<R> win[4 * CAP];
     // consecutive tile rows to one XCD (round-robin dispatch): their windows share L2 lines
     const int nb = gridDim.x;
-    const int nrows = (a.nay + T - 1) / T;
     const int lin = blockIdx.y * nb + blockIdx.x;
     const int xcd = lin % kXcds, slot = lin / kXcds;
-    const int per = (nrows + kXcds - 1) / kXcds;
+    const int per = (a.nty + kXcds - 1) / kXcds;
     const int brow = xcd * per + slot / nb;
-    if (brow >= nrows) return;
-    const int tid = threadIdx.x;
-    const int ax = a.ax0 + (slot % nb) * T + (tid % T);
-    const int ay = a.ay0 + brow * T + tid / T;
-    const bool inr = ax < a.ax0 + a.nax && ay < a.ay0 + a.nay;
+    if (brow >= a.nty) return;
+    const int tx = a.tx0 + slot % nb, ty = a.ty0 + brow;
+    const int tid = threadIdx.x, lx = tid % T, ly = tid / T;
+    const int ax = tx * T + lx, ay = ty * T + ly;
+    const bool inr = ax >= a.ax0 && ax < a.ax0 + a.nax && ay >= a.ay0 && ay < a.ay0 + a.nay;
+    const int hx = a.nx >> 1, hy = a.ny >> 1;
+    // this entry's pre-image (independent of the window: its load overlaps the fill)
     double px, py;
     bool valid;
+    int bx0, bx1, by0, by1;
     if (a.nostretch) {
-        valid = inr && ax <= (a.nx >> 1) && ay <= (a.ny >> 1);
+        valid = inr && ax <= hx && ay <= hy;
         px = valid ? ax : 0.0;
         py = valid ? ay : 0.0;
+        const int lox = max(tx * T, a.ax0), hix = min(min(tx * T + T - 1, a.ax0 + a.nax - 1), hx);
+        const int loy = max(ty * T, a.ay0), hiy = min(min(ty * T + T - 1, a.ay0 + a.nay - 1), hy);
+        bx0 = (lox <= hix && loy <= hiy) ? lox - 1 : INT_MAX;
+        bx1 = hix - 1;
+        by0 = loy - 1;
+        by1 = hiy - 1;
     } else {
         valid = inr && ax <= a.kxt && ay <= a.kyt;
         const int64_t e = valid ? (int64_t)ay * (a.kxt + 1) + ax : 0;
-        const double tx = a.table[2 * e], ty = a.table[2 * e + 1];
-        valid = valid && tx == tx;
+        const double tx_ = a.table[2 * e], ty_ = a.table[2 * e + 1];
+        valid = valid && tx_ == tx_;
         // masked entries (NaN in the table, or beyond it) never reach the index arithmetic
-        px = valid ? tx : 0.0;
-        py = valid ? ty : 0.0;
+        px = valid ? tx_ : 0.0;
+        py = valid ? ty_ : 0.0;
+        bx0 = bx1 = by0 = by1 = INT_MAX;  // a tile beyond the table has no valid entry
+        if (tx < a.tbx && ty < a.tby) {
+            const int4 b = a.bounds[ty * a.tbx + tx];
+            bx0 = b.x;
+            bx1 = b.y;
+            by0 = b.z;
+            by1 = b.w;
+        }
     }
-    const int hx = a.nx >> 1, hy = a.ny >> 1;
-    const double fx = floor(px), fy = floor(py);
-    R wgx[4], wgy[4];
-    keys4<R>(R(px - fx), wgx);
-    keys4<R>(R(py - fy), wgy);
-    // first tap of the (+, +) mirror in spectrum indices, and its extent over the tile's valid entries
-    const int ixp = (int)fx - 1 + hx, iyp = (int)fy - 1 + hy;
-    int r0 = valid ? ixp : INT_MAX, r1 = valid ? -ixp : INT_MAX;
-    int r2 = valid ? iyp : INT_MAX, r3 = valid ? -iyp : INT_MAX;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        r0 = min(r0, __shfl_xor(r0, o));
-        r1 = min(r1, __shfl_xor(r1, o));
-        r2 = min(r2, __shfl_xor(r2, o));
-        r3 = min(r3, __shfl_xor(r3, o));
-    }
-    if ((tid & 63) == 0) {
-        red[tid >> 6][0] = r0;
-        red[tid >> 6][1] = r1;
-        red[tid >> 6][2] = r2;
-        red[tid >> 6][3] = r3;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        r0 = min(r0, red[w][0]);
-        r1 = min(r1, red[w][1]);
-        r2 = min(r2, red[w][2]);
-        r3 = min(r3, red[w][3]);
-    }
-    const bool any = r0 != INT_MAX;  // uniform over the workgroup
-    const int mnx = r0, mxx = -r1, mny = r2, mxy = -r3;
-    // windows: x from mnx (mirror +) or nx - mxx - 3 (mirror -), wx columns; likewise y
+    bx0 = __builtin_amdgcn_readfirstlane(bx0);
+    const bool empty = bx0 == INT_MAX;  // no valid entry in the tile
+    if (empty) bx1 = by0 = by1 = bx0 = 0;
+    const int mnx = __builtin_amdgcn_readfirstlane(bx0) + hx, mxx = __builtin_amdgcn_readfirstlane(bx1) + hx;
+    const int mny = __builtin_amdgcn_readfirstlane(by0) + hy, mxy = __builtin_amdgcn_readfirstlane(by1) + hy;
     const int wx = mxx - mnx + 4, wy = mxy - mny + 4;
-    const bool fits = any && wx <= WXM && wy <= WYM && wx * wy <= CAP;
-    if (fits && sizeof(R) == 4) {
-        // complex64: each lane copies two adjacent samples of a window row with one 16-byte load
-        // (16 lanes per row, 16 rows per pass); a pair that would run off the spectrum's last
-        // column takes its second sample from column 0 (periodic wrap)
-        constexpr int PX = WXM / 2, PR = 256 / PX, KP = (WYM + PR - 1) / PR;
-        typedef R pair_t __attribute__((ext_vector_type(4), aligned(8)));
-        const int c = 2 * (tid % PX), rg = tid / PX;
+    const bool fits = !empty && wx <= P && wy <= WY;
+    // window origins of the mirrors: x from mnx (+) or nx - mxx - 3 (-); likewise y
+    const int xo0 = mnx, xo1 = a.nx - mxx - 3, yo0 = mny, yo1 = a.ny - mxy - 3;
+    constexpr int SPL = sizeof(R) == 4 ? 2 : 1;  // samples per 16-byte load
+    const int wxl = (wx + SPL - 1) / SPL * SPL;
+    const bool inside = min(xo0, xo1) >= 0 && max(xo0, xo1) + wxl <= a.nx && min(yo0, yo1) >= 0 &&
+                        max(yo0, yo1) + wy <= a.ny;
+    if (fits && inside) {
+        // 16-byte row loads from a scalar base per mirror; one lane offset serves the four mirrors
+        constexpr int LPR = 32 / SPL, RG = 256 / LPR, KP = (WY + RG - 1) / RG;
+        typedef typename Load16<R>::type V;
+        const int c = SPL * (tid % LPR), rg = tid / LPR;
         const bool cin = c < wx;
-        pair_t tmp[4][KP];
-        int gcs[4], grs[4][KP];
+        uint32_t off[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int r = rg + k * RG;
+            off[k] = (uint32_t)(((r < wy ? r : 0) * a.nx + (cin ? c : 0)) * ES);  // every lane in bounds
+        }
+        V tmp[4][KP];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const int sx = m & 1, sy = m >> 1;
-            const int x0 = sx ? a.nx - mxx - 3 : mnx, y0 = sy ? a.ny - mxy - 3 : mny;
-            int gc = x0 + (cin ? c : 0);
-            gc = gc < 0 ? gc + a.nx : (gc >= a.nx ? gc - a.nx : gc);
-            gcs[m] = gc;
-            const int gcl = gc == a.nx - 1 ? a.nx - 2 : gc;
+            gbyte* base = uniform_ptr(a.spec + ((int64_t)((m >> 1) ? yo1 : yo0) * a.nx + ((m & 1) ? xo1 : xo0)));
 #pragma unroll
-            for (int k = 0; k < KP; ++k) {
-                const int r = rg + k * PR;
-                int gr = y0 + (r < wy ? r : 0);  // branch-free: every thread loads in bounds
-                gr = gr < 0 ? gr + a.ny : (gr >= a.ny ? gr - a.ny : gr);
-                grs[m][k] = gr;
-                tmp[m][k] = *reinterpret_cast<const pair_t*>(a.spec + (int64_t)gr * a.nx + gcl);
-            }
+            for (int k = 0; k < KP; ++k) tmp[m][k] = load16<V>(base, off[k]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
-                const int r = rg + k * PR;
+                const int r = rg + k * RG;
                 if (cin && r < wy) {
-                    cpx<R> s0 = mk(R(tmp[m][k].x), R(tmp[m][k].y)), s1 = mk(R(tmp[m][k].z), R(tmp[m][k].w));
-                    if (gcs[m] == a.nx - 1) {  // rare: the window crosses the last column
-                        s0 = s1;
-                        s1 = a.spec[(int64_t)grs[m][k] * a.nx];
+                    cpx<R>* d = win + m * CAP + r * P + c;
+                    d[0] = mk(R(tmp[m][k][0]), R(tmp[m][k][1]));
+                    if constexpr (SPL == 2) {
+                        if (c + 1 < wx) d[1] = mk(R(tmp[m][k][2]), R(tmp[m][k][3]));
                     }
-                    win[m][r * wx + c] = s0;
-                    if (c + 1 < wx) win[m][r * wx + c + 1] = s1;
                 }
             }
         __syncthreads();
     } else if (fits) {
-        const int c = tid % WXM, rg = tid / WXM;
+        // the window crosses the spectrum's edge: one sample per lane, periodic indices
+        constexpr int K = (WY + 7) / 8;
+        const int c = tid % 32, rg = tid / 32;
         const bool cin = c < wx;
         cpx<R> tmp[4][K];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const int sx = m & 1, sy = m >> 1;
-            const int x0 = sx ? a.nx - mxx - 3 : mnx, y0 = sy ? a.ny - mxy - 3 : mny;
+            const int x0 = (m & 1) ? xo1 : xo0, y0 = (m >> 1) ? yo1 : yo0;
             int gc = x0 + (cin ? c : 0);
             gc = gc < 0 ? gc + a.nx : (gc >= a.nx ? gc - a.nx : gc);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int r = rg + k * RG;
-                int gr = y0 + (r < wy ? r : 0);  // branch-free: every thread loads in bounds
+                const int r = rg + k * 8;
+                int gr = y0 + (r < wy ? r : 0);
                 gr = gr < 0 ? gr + a.ny : (gr >= a.ny ? gr - a.ny : gr);
                 tmp[m][k] = a.spec[(int64_t)gr * a.nx + gc];
             }
@@ -266,66 +307,83 @@ __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int r = rg + k * RG;
-                if (cin && r < wy) win[m][r * wx + c] = tmp[m][k];
+                const int r = rg + k * 8;
+                if (cin && r < wy) win[m * CAP + r * P + c] = tmp[m][k];
             }
         __syncthreads();
     }
-    const R scale = valid ? R(1) : R(0);
-    const int c0 = valid ? ixp - mnx : 0, rr0 = valid ? iyp - mny : 0;  // (+) mirror window offsets
+    // Keys weights of the (+, +) mirror; products with the centring sign and the mask folded in
+    const double fx = floor(px), fy = floor(py);
+    R wgx[4], wgy[4];
+    keys4<R>(R(px - fx), wgx);
+    keys4<R>(R(py - fy), wgy);
+    const R sg = valid ? (((ax - a.gx0) & 1) ? R(-1) : R(1)) : R(0);
+    R w[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const R yb = wgy[b] * sg;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[b][q] = yb * wgx[q];
+    }
+    // first taps in spectrum indices (masked entries: the window's corner, in range)
+    const int ixp = valid ? (int)fx - 1 + hx : mnx, iyp = valid ? (int)fy - 1 + hy : mny;
+    const int cw0 = ixp - mnx, cw1 = mxx - ixp, rw0 = iyp - mny, rw1 = mxy - iyp;
 #pragma unroll
     for (int sy = 0; sy < 2; ++sy) {
         const int ky = (sy ? -ay : ay) - a.gy0;
         const bool yin = inr && ky >= 0 && ky < a.my && !(sy && ay == 0);
-        R ky4[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) ky4[b] = sy ? wgy[3 - b] : wgy[b];
-        // mirror row offset: (ny - iyp - 3) - (ny - mxy - 3) = mxy - iyp
-        const int r0w = sy ? (valid ? mxy - iyp : 0) : rr0;
+        // output rows of this mirror from a scalar base at the tile's first row in memory order
+        const int row0 = sy ? -(ty * T + T - 1) - a.gy0 : ty * T - a.gy0;
 #pragma unroll
         for (int sx = 0; sx < 2; ++sx) {
             const int kx = (sx ? -ax : ax) - a.gx0;
             const bool in = yin && kx >= 0 && kx < a.mx && !(sx && ax == 0);
-            R kx4[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) kx4[b] = sx ? wgx[3 - b] : wgx[b];
-            cpx<R> v;
+            R re = R(0), im = R(0);
             if (fits) {
-                const int c0w = sx ? (valid ? mxx - ixp : 0) : c0;
-                v = keys_window<R>(win[2 * sy + sx], wx, c0w, r0w, kx4, ky4);
-            } else {
+                const cpx<R>* s0 = win + (2 * sy + sx) * CAP + (sy ? rw1 : rw0) * P + (sx ? cw1 : cw0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const R wt = w[sy ? 3 - b : b][sx ? 3 - q : q];
+                        const cpx<R> t = s0[b * P + q];
+                        re = fma(wt, t.x, re);
+                        im = fma(wt, t.y, im);
+                    }
+            } else if (!empty) {
                 // taps from global memory: first tap (+) ixp, (-) nx - ixp - 3, weights as above
-                cpx<R> acc = mk(R(0), R(0));
                 const int cb = sx ? a.nx - ixp - 3 : ixp, rb = sy ? a.ny - iyp - 3 : iyp;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     int r = rb + b;
                     r = r < 0 ? r + a.ny : (r >= a.ny ? r - a.ny : r);
-                    cpx<R> racc = mk(R(0), R(0));
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         int cc = cb + q;
                         cc = cc < 0 ? cc + a.nx : (cc >= a.nx ? cc - a.nx : cc);
-                        racc = racc + a.spec[(int64_t)r * a.nx + cc] * kx4[q];
+                        const R wt = w[sy ? 3 - b : b][sx ? 3 - q : q];
+                        const cpx<R> t = a.spec[(int64_t)r * a.nx + cc];
+                        re = fma(wt, t.x, re);
+                        im = fma(wt, t.y, im);
                     }
-                    acc = acc + racc * ky4[b];
                 }
-                v = acc;
             }
-            v = v * ((kx & 1) ? -scale : scale);
-            if (in) a.out[(int64_t)ky * a.mx + kx] = v;
+            if (in) {
+                const int col0 = sx ? -(tx * T + T - 1) - a.gx0 : tx * T - a.gx0;
+                gbyte* base = uniform_ptr(a.out + ((int64_t)row0 * a.mx + col0));
+                const uint32_t o = (uint32_t)(((sy ? T - 1 - ly : ly) * a.mx + (sx ? T - 1 - lx : lx)) * ES);
+                store_cpx<R>(base, o, mk(re, im));
+            }
         }
     }
 }
 
 template <typename R>
 hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st) {
-    constexpr int T = kGatherTile;
-    dim3 block(T * T);
-    const int nb = (a.nax + T - 1) / T;
-    const int nrows = (a.nay + T - 1) / T;
-    const int per = (nrows + kXcds - 1) / kXcds;
-    dim3 grid(nb, kXcds * per);
+    if (a.ntx <= 0 || a.nty <= 0) return hipSuccess;
+    dim3 block(kGatherTile * kGatherTile);
+    const int per = (a.nty + kXcds - 1) / kXcds;
+    dim3 grid(a.ntx, kXcds * per);
     hipLaunchKernelGGL(stretch_gather_kernel<R>, grid, block, 0, st, a);
     return hipGetLastError();
 }

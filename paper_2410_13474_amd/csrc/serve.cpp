@@ -199,8 +199,7 @@ static nufds_status_t get_table(nufds_server* S, const nufds_spectrum* sp, hipSt
     t->wavelength = sp->wavelength;
     t->pitch = sp->pitch;
     table_extent(sp->wavelength, sp->pitch, sp->nx, sp->ny, &t->kxt, &t->kyt);
-    const size_t entries = (size_t)(t->kxt + 1) * (t->kyt + 1);
-    NUFDS_TRY(dev_alloc(t->buf, entries * 2 * sizeof(double)));
+    NUFDS_TRY(dev_alloc(t->buf, map_table_bytes(t->kxt, t->kyt)));
     hipError_t e = launch_map_table(static_cast<double*>(t->buf.p), t->kxt, t->kyt, sp->wavelength,
                                     sp->nx * sp->pitch, sp->ny * sp->pitch, sp->wavelength / (2.0 * sp->pitch), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // other slots' streams read it next
