@@ -161,6 +161,9 @@ def parse():
     ap.add_argument("--summarize-profile", default=None, metavar="DIR",
                     help="no GPU: turn rocprofv3 output under DIR (trace/, fetch/, write/, roles.json) "
                          "into the committed summaries under profiles/")
+    ap.add_argument("--no-stack", action="store_true", help="skip the focal-stack run")
+    ap.add_argument("--stack-depths", default="1.0,1.2,1.4",
+                    help="focal-stack depths as multiples of the workload's z")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-inflight", type=int, default=4, help="server workspaces (streams)")
     return ap.parse_args()
@@ -337,6 +340,30 @@ def serving(torch, N, n_requests, inflight=4):
                         "Poisson arrivals at 70% of closed-loop capacity"}
 
 
+def focal_stack(torch, N, H, dp, n, z, factors, steps, warmup, single_ms):
+    """Full views at several depths from one hologram, sharing the z-independent stages (complex64)."""
+    zs = [z * f for f in factors]
+    st = N.Stack(LAM, dp, n, n, zs, precision="c64")
+    outs = [torch.empty((i["sy"], i["sx"]), dtype=torch.complex64, device="cuda") for i in st.infos]
+    for _ in range(max(1, warmup)):
+        st.execute(H, outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        st.execute(H, outs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    d = len(zs)
+    rec = {"depths_m": zs, "frt_size": st.infos[0]["mx"], "ms_per_execute": ms, "ms_per_depth": ms / d,
+           "mpix_s": d * n * n / (ms * 1e-3) / 1e6, "speedup_vs_one_plan_per_depth": d * single_ms / ms}
+    log(f"focal stack {d} depths: {ms:.3f} ms ({ms / d:.3f} ms per depth, "
+        f"{rec['speedup_vs_one_plan_per_depth']:.2f}x one plan per depth)")
+    st.close()
+    return rec
+
+
 def main():
     args = parse()
     if args.summarize_profile:
@@ -417,6 +444,12 @@ def main():
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
 
+    stack = None
+    if not args.no_stack:
+        factors = [float(f) for f in args.stack_depths.split(",")]
+        stack = focal_stack(torch, N, H64, dp, n, z, factors, max(1, min(args.steps, 5)), args.warmup,
+                            main_r["ms_per_step"])
+
     serve = None
     if not args.no_serving:
         serve = serving(torch, N, args.serving_requests, args.serving_inflight)
@@ -451,6 +484,7 @@ def main():
                             "per_step": v["launches_per_step"]} for k, v in r["kernels"].items()}
                     for p, r in results.items()},
         "partial_view_latency_ms": serve,
+        "focal_stack": stack,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -326,6 +326,58 @@ nufds_status_t nufds_server_wait(nufds_server_t server, uint64_t ticket, double*
  * workspaces and tables.  NULL is a no-op. */
 nufds_status_t nufds_server_destroy(nufds_server_t server);
 
+/* ------------------------------------------------------------------ focal stack
+ *
+ * Full views of one hologram at several depths, as in the multi-depth
+ * reconstructions of Sec. 5 (Figs. 8 and 10: the same hologram brought to
+ * focus at two distances).  At the FrT pitch D_F = lambda z / (N D) the
+ * stretched band (steps 1-2, Eqs. 9-10 with Eq. 16) and its inverse DFT do
+ * not depend on z, so a stack computes them once per execute into a cached
+ * array and runs only the z-dependent part per depth: the chirp-in and the
+ * forward DFT of Eq. 2, and the output gather of Eqs. 17-18.  All depths
+ * share one FrT size: the largest the size rule gives over the depths (the
+ * aperture pad N D / 2 is the most samples at the smallest z), so depth i
+ * equals nufds_plan_create_ex at z[i] with that FrT size forced.
+ */
+typedef struct nufds_stack* nufds_stack_t;
+
+/*
+ * nufds_stack_create -- build a focal stack of n_z full views (nx x ny
+ * outputs over B(z) of Eq. 1 each) of an nx x ny hologram.
+ *
+ * z: host array of n_z distances in metres (any order; 1 <= n_z <= 64),
+ * copied.  precision and flags as for nufds_plan_create.  The stack owns
+ * the buffers of one plan at the shared FrT size M_x x M_y plus one cached
+ * M_x M_y array and, per depth, its chirp and output-map vectors.  Uses the
+ * current device.  Errors: INVALID_ARG (NULLs, ranges, as for
+ * nufds_plan_create at each depth), UNSUPPORTED (sizes beyond the kernels),
+ * OUT_OF_MEMORY, HIP.  On error *stack is NULL.
+ */
+nufds_status_t nufds_stack_create(nufds_stack_t* stack, double wavelength, double pitch, int32_t nx,
+                                  int32_t ny, const double* z, int32_t n_z, nufds_precision_t precision,
+                                  uint32_t flags);
+
+/* nufds_stack_info -- geometry of depth i (0 <= i < n_z); workspace_bytes
+ * is the whole stack's.  Errors: INVALID_ARG (NULLs, i out of range). */
+nufds_status_t nufds_stack_info(nufds_stack_t stack, int32_t i, nufds_plan_info_t* out);
+
+/*
+ * nufds_stack_execute -- reconstruct every depth of the stack from one
+ * hologram.
+ *
+ * d_hologram: device [ny][nx] complex of the stack's precision (read only).
+ * d_outs: host array of n_z device pointers, d_outs[i] receiving the
+ * [ny][nx] view of depth i (none may alias the hologram or another).
+ * Enqueued on stream, asynchronous; one execute at a time per stack.
+ * Errors: INVALID_ARG (NULLs, aliasing), HIP.
+ */
+nufds_status_t nufds_stack_execute(nufds_stack_t stack, const void* d_hologram, void* const* d_outs,
+                                   void* stream);
+
+/* nufds_stack_destroy -- wait for the device and free everything the stack
+ * owns.  NULL is a no-op. */
+nufds_status_t nufds_stack_destroy(nufds_stack_t stack);
+
 /* nufds_status_string -- static text of a status code. */
 const char* nufds_status_string(nufds_status_t status);
 

@@ -49,7 +49,7 @@ __all__ = [
     "output_map", "output_map_inverse_eq18b",
     "keys_weight", "smooth5_even", "Band", "plan_band",
     "centred_dft2", "centred_idft2", "centred_dft2_direct",
-    "stretch_gather", "fresnel_frt", "reconstruct",
+    "stretch_gather", "fresnel_frt", "reconstruct", "focal_stack",
     "rayleigh_sommerfeld_backprop", "rel_l2",
 ]
 
@@ -630,6 +630,24 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
     if return_stages:
         return O, dict(band=band, spectrum=Hs, stretched=Ht, h=h, F=F, xp=XP, yp=YP)
     return O
+
+
+def focal_stack(H, wavelength, pitch, zs, flags=0):
+    """Full views of hologram ``H`` at each distance in ``zs``, with one FrT size for all of them.
+
+    The paper reconstructs one hologram at several depths (Sec. 5, Figs. 8 and 10).  At the FrT
+    pitch Delta_F = lambda z / (N Delta) the spectral pitch of the stretched band is 1 / (N Delta)
+    whatever z, so steps 1-2 (the stretch of Eqs. 9-10 with Eq. 16 and the inverse transform) give
+    the same array for every depth that shares the band.  Reading: the shared FrT size is the
+    largest the band rule gives over the depths (the aperture pad N Delta / 2 spans the most FrT
+    samples at the smallest z); each depth is then ``reconstruct`` at its z with that size forced.
+    Returns the list of [ny, nx] complex128 views in the order of ``zs``.
+    """
+    H = np.asarray(H, dtype=np.complex128)
+    ny, nx = H.shape
+    bands = [plan_band(nx, ny, wavelength, pitch, z, None, flags) for z in zs]
+    size = (max(b.mx for b in bands), max(b.my for b in bands))
+    return [reconstruct(H, wavelength, pitch, z, flags=flags, frt_size=size) for z in zs]
 
 
 # --------------------------------------------------------------------------

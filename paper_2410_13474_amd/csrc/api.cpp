@@ -618,6 +618,60 @@ nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, h
     return NUFDS_OK;
 }
 
+// Step 5: output gather from the FrT F ([my][mx], centring signs applied) into d_out.
+template <typename R>
+static nufds_status_t run_output_gather(nufds_plan* p, const void* F, void* d_out, hipStream_t s) {
+    const nufds_plan_info_t& g = p->info;
+    const int mx = g.mx, my = g.my;
+    const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
+    OutputArgs<R> oa;
+    oa.F = static_cast<const cpx<R>*>(F);
+    oa.out = static_cast<cpx<R>*>(d_out);
+    oa.ax = static_cast<const double*>(p->ax.p);
+    oa.by = static_cast<const double*>(p->by.p);
+    oa.sx = g.sx;
+    oa.sy = g.sy;
+    oa.mx = mx;
+    oa.my = my;
+    oa.kcx = g.kcx;
+    oa.kcy = g.kcy;
+    oa.cx = g.cx;
+    oa.cy = g.cy;
+    oa.dox = g.dox;
+    oa.doy = g.doy;
+    oa.inv_dfx = 1.0 / g.dfx;
+    oa.inv_dfy = 1.0 / g.dfy;
+    oa.qx0 = (double)(mx / 2) - (double)g.kcx;
+    oa.qy0 = (double)(my / 2) - (double)g.kcy;
+    oa.z = p->z;
+    oa.kz2 = (2.0 * M_PI / p->wavelength) / (2.0 * p->z);
+    oa.remap = (p->flags & NUFDS_FLAG_NO_REMAP) ? 0 : 1;
+    oa.conj_out = conj_in;
+    // algorithmic bytes: the FrT samples under the window's distorted image (plus the 4-tap
+    // support), read once, and the output written once
+    const double fxs = std::min((double)mx, (g.xhi - g.xlo) / g.dfx + 4.0);
+    const double fys = std::min((double)my, (g.yhi - g.ylo) / g.dfy + 4.0);
+    const uint64_t obytes = (uint64_t)(fxs * fys) * sizeof(cpx<R>) + (uint64_t)g.sx * g.sy * sizeof(cpx<R>);
+    NUFDS_TRY(timing_begin(p, "output_gather", obytes, s));
+    NUFDS_HIP_TRY(launch_output_gather<R>(oa, s));
+    return timing_end(p, s);
+}
+
+// One DFT of length L along an axis of a [rows][pitch] array without chain: a single pass from in to
+// out, or the four-step A pass into work and the B pass into out.  load_sign / store_sign apply the
+// centring factor (-1)^index on the input / output axis.
+template <typename R>
+static nufds_status_t run_transform(nufds_plan* p, const char* name_a, const char* name_b, int axis, int L, int other,
+                                    int64_t pitch, int sign, const void* in, void* work, void* out, int load_sign,
+                                    int store_sign, hipStream_t s) {
+    const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
+    AxisPlan ap;
+    if (!build_axis(axis, L, other, pitch, sign, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "transform length");
+    if (ap.single) return run_pass<R>(p, name_a, ap.passes[0], in, out, 0, load_sign, store_sign, R(1), nullptr, s);
+    NUFDS_TRY(run_pass<R>(p, name_a, ap.passes[0], in, work, 0, load_sign, 0, R(1), nullptr, s));
+    return run_pass<R>(p, name_b, ap.passes[1], work, out, 0, 0, store_sign, R(1), nullptr, s);
+}
+
 template <typename R>
 nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
@@ -625,7 +679,6 @@ nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_
     const int mx = g.mx, my = g.my;
     void* w1 = p->work1.p;
     void* w2 = p->work2.p;
-    const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
     AxisPlan ap;
 
     // steps 2b-3 along x: stretch-gather, centred IDFT, chirp / M_x, centred DFT (signs cancel to
@@ -660,39 +713,7 @@ nufds_status_t run_band(nufds_plan* p, const void* spec, void* d_out, hipStream_
         res = oth;
     }
     p->result = res;
-
-    // step 5: output gather
-    OutputArgs<R> oa;
-    oa.F = static_cast<const cpx<R>*>(res);
-    oa.out = static_cast<cpx<R>*>(d_out);
-    oa.ax = static_cast<const double*>(p->ax.p);
-    oa.by = static_cast<const double*>(p->by.p);
-    oa.sx = g.sx;
-    oa.sy = g.sy;
-    oa.mx = mx;
-    oa.my = my;
-    oa.kcx = g.kcx;
-    oa.kcy = g.kcy;
-    oa.cx = g.cx;
-    oa.cy = g.cy;
-    oa.dox = g.dox;
-    oa.doy = g.doy;
-    oa.inv_dfx = 1.0 / g.dfx;
-    oa.inv_dfy = 1.0 / g.dfy;
-    oa.qx0 = (double)(mx / 2) - (double)g.kcx;
-    oa.qy0 = (double)(my / 2) - (double)g.kcy;
-    oa.z = p->z;
-    oa.kz2 = (2.0 * M_PI / p->wavelength) / (2.0 * p->z);
-    oa.remap = (p->flags & NUFDS_FLAG_NO_REMAP) ? 0 : 1;
-    oa.conj_out = conj_in;
-    // algorithmic bytes: the FrT samples under the window's distorted image (plus the 4-tap
-    // support), read once, and the output written once
-    const double fxs = std::min((double)mx, (g.xhi - g.xlo) / g.dfx + 4.0);
-    const double fys = std::min((double)my, (g.yhi - g.ylo) / g.dfy + 4.0);
-    const uint64_t obytes = (uint64_t)(fxs * fys) * sizeof(cpx<R>) + (uint64_t)g.sx * g.sy * sizeof(cpx<R>);
-    NUFDS_TRY(timing_begin(p, "output_gather", obytes, s));
-    NUFDS_HIP_TRY(launch_output_gather<R>(oa, s));
-    return timing_end(p, s);
+    return run_output_gather<R>(p, res, d_out, s);
 }
 
 template <typename R>
@@ -725,9 +746,23 @@ template nufds_status_t run_band<double>(nufds_plan*, const void*, void*, hipStr
 template nufds_status_t prepare_twiddles<float>(nufds_plan*, bool, bool);
 template nufds_status_t prepare_twiddles<double>(nufds_plan*, bool, bool);
 
+// Output-map factors A(x_j), B(y_i) of Eqs. 17-18 for the plan's output grid, float64 on the host.
+static nufds_status_t upload_output_map(nufds_plan* p) {
+    if (p->flags & NUFDS_FLAG_NO_REMAP) return NUFDS_OK;
+    const nufds_plan_info_t& g = p->info;
+    std::vector<double> ax(g.sx), by(g.sy);
+    for (int j = 0; j < g.sx; ++j) ax[j] = output_map_factor(g.cx + (double)(j - g.sx / 2) * g.dox, p->z);
+    for (int i = 0; i < g.sy; ++i) by[i] = output_map_factor(g.cy + (double)(i - g.sy / 2) * g.doy, p->z);
+    NUFDS_TRY(dev_alloc(p->ax, g.sx * sizeof(double)));
+    NUFDS_TRY(dev_alloc(p->by, g.sy * sizeof(double)));
+    NUFDS_HIP_TRY(hipMemcpy(p->ax.p, ax.data(), p->ax.bytes, hipMemcpyHostToDevice));
+    NUFDS_HIP_TRY(hipMemcpy(p->by.p, by.data(), p->by.bytes, hipMemcpyHostToDevice));
+    return NUFDS_OK;
+}
+
+// Chirp vectors of the plan's depth, one per axis (each carrying the 1/M of its inverse DFT).
 template <typename R>
-static nufds_status_t prepare_impl(nufds_plan* p) {
-    NUFDS_TRY(prepare_twiddles<R>(p, true, true));
+static nufds_status_t upload_chirps(nufds_plan* p) {
     const nufds_plan_info_t& g = p->info;
     std::vector<double> re, im;
     chirp_vector(g.mx, g.nx, p->pitch, p->wavelength, p->z, re, im);
@@ -735,6 +770,12 @@ static nufds_status_t prepare_impl(nufds_plan* p) {
     chirp_vector(g.my, g.ny, p->pitch, p->wavelength, p->z, re, im);
     NUFDS_TRY(upload_complex<R>(p->chirp_y, re, im));
     return NUFDS_OK;
+}
+
+template <typename R>
+static nufds_status_t prepare_impl(nufds_plan* p) {
+    NUFDS_TRY(prepare_twiddles<R>(p, true, true));
+    return upload_chirps<R>(p);
 }
 
 static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, double pitch, int32_t nx, int32_t ny,
@@ -788,17 +829,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
                               nullptr);
         if (he != hipSuccess) return bail(hip_fail(he, "map table launch"));
     }
-    // output-map factors A(x_j), B(y_i) (Eqs. 17-18), float64 on the host
-    if (!(flags & NUFDS_FLAG_NO_REMAP)) {
-        std::vector<double> ax(g.sx), by(g.sy);
-        for (int j = 0; j < g.sx; ++j) ax[j] = output_map_factor(g.cx + (double)(j - g.sx / 2) * g.dox, z);
-        for (int i = 0; i < g.sy; ++i) by[i] = output_map_factor(g.cy + (double)(i - g.sy / 2) * g.doy, z);
-        if ((st = dev_alloc(p->ax, g.sx * sizeof(double))) != NUFDS_OK) return bail(st);
-        if ((st = dev_alloc(p->by, g.sy * sizeof(double))) != NUFDS_OK) return bail(st);
-        he = hipMemcpy(p->ax.p, ax.data(), p->ax.bytes, hipMemcpyHostToDevice);
-        if (he == hipSuccess) he = hipMemcpy(p->by.p, by.data(), p->by.bytes, hipMemcpyHostToDevice);
-        if (he != hipSuccess) return bail(hip_fail(he, "hipMemcpy(output map)"));
-    }
+    if ((st = upload_output_map(p)) != NUFDS_OK) return bail(st);
     st = precision == NUFDS_C64 ? prepare_impl<float>(p) : prepare_impl<double>(p);
     if (st != NUFDS_OK) return bail(st);
     he = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
@@ -875,7 +906,182 @@ static nufds_status_t execute_common(nufds_plan_t plan, const void* d_hologram, 
     return NUFDS_OK;
 }
 
+// ------------------------------------------------------------ focal stack
+struct nufds_stack {
+    nufds_plan* base = nullptr;      // full plan of depth 0 at the shared FrT size: spectrum, work, table
+    std::vector<nufds_plan*> depth;  // per depth: geometry, chirps, output map (depth[0] is base)
+    nufds::DevBuf cache;             // inverse DFT of the stretched band, [my][mx]
+    size_t bytes = 0;
+};
+
+// A depth of a stack: its own geometry, chirp vectors and output-map factors; the spectrum, work
+// buffers, map table and twiddles are the base plan's.
+static nufds_status_t depth_plan(nufds_plan* base, double z, const nufds_options_t* opt, nufds_plan** out) {
+    *out = nullptr;
+    nufds_plan_info_t g;
+    NUFDS_TRY(compute_geometry(base->wavelength, base->pitch, base->info.nx, base->info.ny, z, nullptr, base->flags,
+                               opt, &g));
+    if (g.mx != base->info.mx || g.my != base->info.my || g.kcx != base->info.kcx || g.kcy != base->info.kcy)
+        return fail(NUFDS_ERR_UNSUPPORTED, "the depths do not share one band");
+    nufds_plan* p = new (std::nothrow) nufds_plan();
+    if (!p) return fail(NUFDS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->info = g;
+    p->info.precision = base->info.precision;
+    p->wavelength = base->wavelength;
+    p->pitch = base->pitch;
+    p->z = z;
+    p->flags = base->flags;
+    p->prec = base->prec;
+    p->esize = base->esize;
+    p->device = base->device;
+    p->tile_cap = base->tile_cap;
+    p->col_w = base->col_w;
+    p->twiddles = base->twiddles;
+    p->spec = borrow(base->spec.p, base->spec.bytes);
+    p->work1 = borrow(base->work1.p, base->work1.bytes);
+    p->work2 = borrow(base->work2.p, base->work2.bytes);
+    p->table = borrow(base->table.p, base->table.bytes);
+    p->kxt = base->kxt;
+    p->kyt = base->kyt;
+    nufds_status_t st = upload_output_map(p);
+    if (st == NUFDS_OK) st = p->prec == NUFDS_C64 ? upload_chirps<float>(p) : upload_chirps<double>(p);
+    if (st != NUFDS_OK) {
+        std::string msg = nufds_last_error();
+        plan_free(p);
+        set_error(msg);
+        return st;
+    }
+    *out = p;
+    return NUFDS_OK;
+}
+
+// Steps 2-2c once (FFT of the hologram, stretch-gather, inverse DFT of the band along x then y, kept
+// in the cache), then per depth the chirp-in and the centred forward DFT of Eq. 2 and the output
+// gather.  Centring: the gather carries (-1)^k'_x and the y inverse DFT applies (-1)^k'_y on load;
+// the (-1)^(n + M/2) of each inverse DFT's output cancels against the (-1)^n of the forward DFT's
+// input (M even), which leaves (-1)^m on the forward DFT's output.
+template <typename R>
+static nufds_status_t run_stack(nufds_stack* S, const void* d_hologram, void* const* d_outs, hipStream_t s) {
+    nufds_plan* b = S->base;
+    const int mx = b->info.mx, my = b->info.my;
+    char* w1 = static_cast<char*>(b->work1.p);
+    char* w2 = static_cast<char*>(b->work2.p);
+    void* q = S->cache.p;
+    NUFDS_TRY(run_fft1<R>(b, d_hologram, b->spec.p, w1, s));
+    NUFDS_TRY(run_stretch_gather<R>(b, b->spec.p, w2, s));
+    NUFDS_TRY(run_transform<R>(b, "idft_x_a", "idft_x_b", 0, mx, my, mx, +1, w2, w1, w2, 0, 0, s));
+    NUFDS_TRY(run_transform<R>(b, "idft_y_a", "idft_y_b", 1, my, mx, mx, +1, w2, w1, q, 1, 0, s));
+    for (size_t i = 0; i < S->depth.size(); ++i) {
+        nufds_plan* d = S->depth[i];
+        NUFDS_HIP_TRY(launch_chirp2d<R>(static_cast<const cpx<R>*>(q), reinterpret_cast<cpx<R>*>(w1),
+                                        static_cast<const cpx<R>*>(d->chirp_x.p),
+                                        static_cast<const cpx<R>*>(d->chirp_y.p), mx, my, s));
+        NUFDS_TRY(run_transform<R>(d, "dft_x_a", "dft_x_b", 0, mx, my, mx, -1, w1, w2, w1, 0, 1, s));
+        // only the columns this depth's output gather reads need the y transform
+        const size_t coff = (size_t)d->info.fcx0 * sizeof(cpx<R>);
+        NUFDS_TRY(run_transform<R>(d, "dft_y_a", "dft_y_b", 1, my, d->info.fcxn, mx, -1, w1 + coff, w2 + coff,
+                                   w1 + coff, 0, 1, s));
+        NUFDS_TRY(run_output_gather<R>(d, w1, d_outs[i], s));
+    }
+    b->result = w1;
+    return NUFDS_OK;
+}
+
+static void stack_free(nufds_stack* S) {
+    if (!S) return;
+    (void)hipDeviceSynchronize();
+    for (nufds_plan* d : S->depth)
+        if (d != S->base) plan_free(d);
+    plan_free(S->base);
+    dev_free(S->cache);
+    delete S;
+}
+
+static nufds_status_t stack_create_impl(nufds_stack_t* out, double wavelength, double pitch, int32_t nx, int32_t ny,
+                                        const double* z, int32_t n_z, nufds_precision_t precision, uint32_t flags) {
+    if (!out) return fail(NUFDS_ERR_INVALID_ARG, "stack is NULL");
+    *out = nullptr;
+    if (!z || n_z < 1 || n_z > 64) return fail(NUFDS_ERR_INVALID_ARG, "a stack has 1 to 64 depths");
+    // the shared FrT size: the largest the size rule gives over the depths
+    nufds_options_t opt;
+    opt.pad = -1.0;
+    opt.frt_size_x = opt.frt_size_y = 0;
+    for (int i = 0; i < n_z; ++i) {
+        nufds_plan_info_t g;
+        NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z[i], nullptr, flags, nullptr, &g));
+        opt.frt_size_x = std::max(opt.frt_size_x, g.mx);
+        opt.frt_size_y = std::max(opt.frt_size_y, g.my);
+    }
+    nufds_stack* S = new (std::nothrow) nufds_stack();
+    if (!S) return fail(NUFDS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    auto bail = [&](nufds_status_t st) {
+        std::string msg = nufds_last_error();
+        stack_free(S);
+        set_error(msg);
+        return st;
+    };
+    nufds_plan_t base = nullptr;
+    nufds_status_t st = plan_create_impl(&base, wavelength, pitch, nx, ny, z[0], nullptr, precision, flags, &opt);
+    if (st != NUFDS_OK) return bail(st);
+    S->base = base;
+    S->depth.push_back(base);
+    if ((st = dev_alloc(S->cache, (size_t)base->info.mx * base->info.my * base->esize)) != NUFDS_OK) return bail(st);
+    S->bytes = base->info.workspace_bytes + S->cache.bytes;
+    for (int i = 1; i < n_z; ++i) {
+        nufds_plan* d = nullptr;
+        if ((st = depth_plan(base, z[i], &opt, &d)) != NUFDS_OK) return bail(st);
+        S->depth.push_back(d);
+        S->bytes += d->chirp_x.bytes + d->chirp_y.bytes + d->ax.bytes + d->by.bytes;
+    }
+    *out = S;
+    return NUFDS_OK;
+}
+
 extern "C" {
+
+nufds_status_t nufds_stack_create(nufds_stack_t* stack, double wavelength, double pitch, int32_t nx, int32_t ny,
+                                  const double* z, int32_t n_z, nufds_precision_t precision, uint32_t flags) {
+    return stack_create_impl(stack, wavelength, pitch, nx, ny, z, n_z, precision, flags);
+}
+
+nufds_status_t nufds_stack_info(nufds_stack_t stack, int32_t i, nufds_plan_info_t* out) {
+    if (!stack || !out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    if (i < 0 || i >= (int32_t)stack->depth.size()) return fail(NUFDS_ERR_INVALID_ARG, "depth index out of range");
+    *out = stack->depth[i]->info;
+    out->workspace_bytes = stack->bytes;
+    out->map_bytes = stack->base->table.bytes;
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_stack_execute(nufds_stack_t stack, const void* d_hologram, void* const* d_outs, void* stream) {
+    if (!stack || !d_hologram || !d_outs) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");
+    const size_t n = stack->depth.size();
+    for (size_t i = 0; i < n; ++i) {
+        if (!d_outs[i]) return fail(NUFDS_ERR_INVALID_ARG, "NULL output");
+        if (d_outs[i] == d_hologram) return fail(NUFDS_ERR_INVALID_ARG, "an output aliases the hologram");
+        for (size_t j = 0; j < i; ++j)
+            if (d_outs[j] == d_outs[i]) return fail(NUFDS_ERR_INVALID_ARG, "two outputs alias");
+    }
+    nufds_plan* b = stack->base;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->has_run && s != b->last_stream) {
+        hipError_t q = hipEventQuery(b->done);
+        if (q == hipErrorNotReady) return fail(NUFDS_ERR_BUSY, "previous execute still running on another stream");
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    nufds_status_t st = b->prec == NUFDS_C64 ? run_stack<float>(stack, d_hologram, d_outs, s)
+                                              : run_stack<double>(stack, d_hologram, d_outs, s);
+    if (st != NUFDS_OK) return st;
+    NUFDS_HIP_TRY(hipEventRecord(b->done, s));
+    b->last_stream = s;
+    b->has_run = true;
+    return NUFDS_OK;
+}
+
+nufds_status_t nufds_stack_destroy(nufds_stack_t stack) {
+    stack_free(stack);
+    return NUFDS_OK;
+}
 
 nufds_status_t nufds_execute(nufds_plan_t plan, const void* d_hologram, void* d_out, void* stream) {
     if (!plan || !d_hologram || !d_out) return fail(NUFDS_ERR_INVALID_ARG, "NULL argument");

@@ -492,6 +492,36 @@ hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st) {
 template hipError_t launch_output_gather<float>(const OutputArgs<float>&, hipStream_t);
 template hipError_t launch_output_gather<double>(const OutputArgs<double>&, hipStream_t);
 
+// ------------------------------------------------------------ chirp-in of a cached band
+// Multiplies the inverse DFT of the stretched band by one depth's separable chirp of Eq. 2 (each
+// axis' vector already carries 1/M): a plain streaming pass, one element per lane, rows strided over
+// the grid.
+template <typename R>
+__global__ void chirp2d_kernel(const cpx<R>* in, cpx<R>* out, const cpx<R>* __restrict__ cx,
+                               const cpx<R>* __restrict__ cy, int mx, int my) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= mx) return;
+    const cpx<R> c = cx[x];
+    for (int y = blockIdx.y; y < my; y += gridDim.y) {
+        const int64_t e = (int64_t)y * mx + x;
+        out[e] = (in[e] * c) * cy[y];
+    }
+}
+
+template <typename R>
+hipError_t launch_chirp2d(const cpx<R>* in, cpx<R>* out, const cpx<R>* cx, const cpx<R>* cy, int mx, int my,
+                          hipStream_t st) {
+    if (mx <= 0 || my <= 0) return hipSuccess;
+    dim3 block(256);
+    dim3 grid((mx + 255) / 256, my < 8192 ? my : 8192);
+    hipLaunchKernelGGL(chirp2d_kernel<R>, grid, block, 0, st, in, out, cx, cy, mx, my);
+    return hipGetLastError();
+}
+template hipError_t launch_chirp2d<float>(const cpx<float>*, cpx<float>*, const cpx<float>*, const cpx<float>*, int,
+                                          int, hipStream_t);
+template hipError_t launch_chirp2d<double>(const cpx<double>*, cpx<double>*, const cpx<double>*, const cpx<double>*,
+                                           int, int, hipStream_t);
+
 // ------------------------------------------------------------ test input
 // H[i][j] = sum_p a_p exp(i (k r + phi_p)) / r in float64, rounded to R on store.
 template <typename R>

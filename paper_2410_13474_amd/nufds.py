@@ -105,6 +105,13 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_double)]),
     "nufds_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
     "nufds_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "nufds_stack_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_int32, ctypes.c_int, ctypes.c_uint32]),
+    "nufds_stack_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(PlanInfo)]),
+    "nufds_stack_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_void_p]),
+    "nufds_stack_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "nufds_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "nufds_last_error": (ctypes.c_char_p, []),
 }
@@ -360,6 +367,68 @@ class Server:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.nufds_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stack:
+    """Full views of one hologram at several depths sharing the z-independent stages (one FFT of the
+    hologram, stretch-gather and inverse DFT per execute; chirp, DFT and output gather per depth)."""
+
+    def __init__(self, wavelength, pitch, nx, ny, zs, precision="c64", flags=0):
+        lib = load()
+        self._lib = lib
+        self.precision = {"c64": C64, "c128": C128}[precision]
+        zs = [float(z) for z in zs]
+        arr = (ctypes.c_double * max(1, len(zs)))(*zs)
+        handle = ctypes.c_void_p()
+        _check(lib.nufds_stack_create(ctypes.byref(handle), float(wavelength), float(pitch), int(nx), int(ny), arr,
+                                      len(zs), self.precision, int(flags)))
+        self._h = handle
+        self.zs = zs
+        self.infos = []
+        for i in range(len(zs)):
+            info = PlanInfo()
+            _check(lib.nufds_stack_info(self._h, i, ctypes.byref(info)))
+            self.infos.append(info.as_dict())
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex64 if self.precision == C64 else torch.complex128
+
+    def execute(self, hologram, outs, stream=None) -> None:
+        """Enqueue every depth of the stack from device tensor ``hologram`` into ``outs`` (one per depth)."""
+        i0 = self.infos[0]
+        if hologram.dtype != self.dtype or tuple(hologram.shape) != (i0["ny"], i0["nx"]):
+            raise ValueError("hologram must match the stack's precision and size")
+        if len(outs) != len(self.zs):
+            raise ValueError("one output per depth")
+        for o, info in zip(outs, self.infos):
+            if o.dtype != self.dtype or tuple(o.shape) != (info["sy"], info["sx"]) or not (o.is_cuda and
+                                                                                          o.is_contiguous()):
+                raise ValueError("outputs must be contiguous device tensors of each depth's shape and precision")
+        if not (hologram.is_cuda and hologram.is_contiguous()):
+            raise ValueError("hologram must be a contiguous device tensor")
+        ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        _check(self._lib.nufds_stack_execute(self._h, ctypes.c_void_p(hologram.data_ptr()), ptrs,
+                                             _stream_handle(stream)))
+
+    def __call__(self, hologram, outs=None, stream=None):
+        import torch
+        if outs is None:
+            outs = [torch.empty((i["sy"], i["sx"]), dtype=self.dtype, device=hologram.device) for i in self.infos]
+        self.execute(hologram, outs, stream)
+        return outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nufds_stack_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -176,6 +176,27 @@ def test_serving_entry_points_reject_invalid_arguments():
     assert lib.nufds_server_destroy(None) == N.OK
 
 
+def test_stack_entry_points_reject_invalid_arguments():
+    """Focal-stack checks that fail before any HIP call (geometry is validated on the host)."""
+    lib = N.load()
+    zs = (ctypes.c_double * 3)(1.0e-3, 1.5e-3, 2.0e-3)
+    h = ctypes.c_void_p(1234)
+    assert lib.nufds_stack_create(None, 0.5e-6, 0.5e-6, 64, 64, zs, 3, 0, 0) == N.ERR_INVALID_ARG
+    assert lib.nufds_stack_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, None, 3, 0, 0) == N.ERR_INVALID_ARG
+    assert h.value is None
+    for n in (0, -1, 65):
+        assert lib.nufds_stack_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, zs, n, 0, 0) == N.ERR_INVALID_ARG
+    bad_z = (ctypes.c_double * 2)(1.0e-3, -1.0e-3)
+    assert lib.nufds_stack_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 64, 64, bad_z, 2, 0, 0) == N.ERR_INVALID_ARG
+    assert lib.nufds_stack_create(ctypes.byref(h), 0.5e-6, 0.5e-6, 63, 64, zs, 3, 0, 0) == N.ERR_INVALID_ARG
+    assert lib.nufds_stack_create(ctypes.byref(h), 0.5e-6, 0.2e-6, 64, 64, zs, 3, 0, 0) == N.ERR_INVALID_ARG
+    assert h.value is None
+    info = N.PlanInfo()
+    assert lib.nufds_stack_info(None, 0, ctypes.byref(info)) == N.ERR_INVALID_ARG
+    assert lib.nufds_stack_execute(None, None, None, None) == N.ERR_INVALID_ARG
+    assert lib.nufds_stack_destroy(None) == N.OK
+
+
 def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(N, "_lib", None)
     monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "missing.so"))

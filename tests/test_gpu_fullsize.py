@@ -113,3 +113,30 @@ def test_fullsize_point_focus(where):
     # aberration at this geometry spreads it over a few samples; see the docstring)
     assert float(a.max()) > 20.0 * float(a.mean())
     plan.close()
+
+
+def test_fullsize_focal_stack_matches_plans():
+    """16384^2 / 120 deg (the benchmark's hologram), depths 15 and 20 mm sharing the FrT size of the
+    nearer one (M = 25600): each depth against a complex64 plan at that depth with the same size
+    (the same method through the chained passes; float32 rounding apart, rel-L2 <= 1e-5)."""
+    say("full size focal stack")
+    n = 16384
+    dp, H128 = _gpu_hologram(n, 120.0, 1003, 1024, 10e-3, 20e-3)
+    H = H128.to(torch.complex64)
+    del H128
+    zs = [15e-3, 20e-3]
+    st = N.Stack(LAM, dp, n, n, zs, precision="c64")
+    assert {(i["mx"], i["my"]) for i in st.infos} == {(25600, 25600)}
+    outs = st(H)
+    torch.cuda.synchronize()
+    for z, o, info in zip(zs, outs, st.infos):
+        assert torch.isfinite(torch.view_as_real(o)).all()
+        plan = N.Plan(LAM, dp, n, n, z, precision="c64", frt_size=(info["mx"], info["my"]))
+        ref = plan(H)
+        torch.cuda.synchronize()
+        err = _rel(o, ref)
+        say(f"  z {z * 1e3:.1f} mm: rel L2 stack vs plan {err:.3e}")
+        assert err <= 1e-5
+        plan.close()
+        del ref
+    st.close()

@@ -73,3 +73,25 @@ def test_unconjugated_input_is_caught(monkeypatch):
     _patch(monkeypatch, "reconstruct", bad_reconstruct)
     with pytest.raises(AssertionError):
         pins.test_point_focuses_at_its_true_position(60.0, 0.5)
+
+
+def test_stack_sharing_the_smallest_size_is_caught(monkeypatch):
+    def bad_stack(H, wavelength, pitch, zs, flags=0):
+        H = np.asarray(H, dtype=np.complex128)
+        ny, nx = H.shape
+        bands = [mod.plan_band(nx, ny, wavelength, pitch, z, None, flags) for z in zs]
+        size = (min(b.mx for b in bands), min(b.my for b in bands))   # smallest instead of largest
+        return [mod.reconstruct(H, wavelength, pitch, z, flags=flags, frt_size=size) for z in zs]
+    _patch(monkeypatch, "focal_stack", bad_stack)
+    with pytest.raises(AssertionError):
+        pins.test_focal_stack_focuses_a_point_at_its_depth()
+
+
+def test_stack_in_sorted_depth_order_is_caught(monkeypatch):
+    good = mod.focal_stack
+
+    def bad_stack(H, wavelength, pitch, zs, flags=0):
+        return good(H, wavelength, pitch, sorted(zs), flags)
+    _patch(monkeypatch, "focal_stack", bad_stack)
+    with pytest.raises(AssertionError):
+        pins.test_focal_stack_focuses_a_point_at_its_depth()

@@ -446,6 +446,37 @@ def test_focus_is_sharpest_at_the_point_depth():
     assert peaks[0.96] < peaks[0.98] < peaks[1.0] > peaks[1.02] > peaks[1.04]
 
 
+def test_focal_stack_single_depth_is_the_reconstruction():
+    lam, dp, zp, xp, yp, H = _spot(90.0, 0.5, n=64, ratio=5.0)
+    a = O.focal_stack(H, lam, dp, [zp])[0]
+    assert np.array_equal(a, O.reconstruct(H, lam, dp, zp))
+
+
+def test_focal_stack_focuses_a_point_at_its_depth():
+    """A depth scan through one on-axis point with the FrT size of the nearest depth forced on all
+    (192 against the focus depth's own 180): the intensity (Fresnel number of the defocus about 1
+    at 10 %, 2-3 at 20-25 %) peaks at the point's depth and falls on both sides, and the focus sits
+    on the axis pixel.  The depths are given out of order: the views follow the order of the
+    distances."""
+    lam, dp, zp, xp, yp, H = _spot(60.0, 0.0, n=128, ratio=3.0)
+    n = H.shape[0]
+    fs = [1.1, 0.8, 1.0, 1.25, 0.9]
+    outs = O.focal_stack(H, lam, dp, [zp * f for f in fs])
+    peaks = np.array([np.max(np.abs(o) ** 2) for o in outs])
+    k = fs.index(1.0)
+    assert int(np.argmax(peaks)) == k
+    p = peaks[np.argsort(fs)]
+    assert p[0] < p[1] < p[2] > p[3] > p[4]
+    I = np.abs(outs[k]) ** 2
+    assert np.unravel_index(I.argmax(), I.shape) == (n // 2, n // 2)
+    # the shared size is the nearest depth's, larger than the focus depth's own: the nearest view is
+    # its own reconstruction, the focus view is not
+    bands = [O.plan_band(n, n, lam, dp, zp * f) for f in fs]
+    assert max(b.mx for b in bands) == bands[fs.index(0.8)].mx > bands[k].mx
+    assert np.array_equal(outs[fs.index(0.8)], O.reconstruct(H, lam, dp, zp * 0.8))
+    assert not np.allclose(outs[k], O.reconstruct(H, lam, dp, zp), rtol=0, atol=1e-6 * np.abs(outs[k]).max())
+
+
 @pytest.mark.parametrize("fov", [60.0, 90.0, 120.0])
 def test_against_rayleigh_sommerfeld(fov):
     """Brute-force RS back-propagation on a tiny grid: same focus, >= 80% of its concentration.
