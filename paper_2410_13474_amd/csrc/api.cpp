@@ -523,7 +523,7 @@ static uint64_t pass_bytes(const PassDesc& d, size_t esize) { return 2ull * d.ro
 template <typename R>
 static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& d, const void* in, void* out,
                                int load_conj, int load_sign, int store_sign, R store_scale,
-                               const cpx<R>* chainvec, hipStream_t s) {
+                               const cpx<R>* chainvec, hipStream_t s, const cpx<R>* load_mul = nullptr) {
     const cpx<R>* tw;
     nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
     if (st != NUFDS_OK) return st;
@@ -532,7 +532,8 @@ static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& 
         st = twiddle_table<R>(p, d.Lf, &twf);
         if (st != NUFDS_OK) return st;
     }
-    LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1), (!load_conj && !load_sign) ? 1 : 0};
+    LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1),
+                    (!load_conj && !load_sign && !load_mul) ? 1 : 0, load_mul};
     StorePlain<R> sto{static_cast<cpx<R>*>(out), store_sign, store_scale, (!store_sign && store_scale == R(1)) ? 1 : 0};
     NUFDS_TRY(timing_begin(p, name, pass_bytes(d, sizeof(cpx<R>)), s));
     NUFDS_HIP_TRY((launch_pass<R>(d, ld, sto, tw, twf, chainvec, s)));
@@ -659,16 +660,18 @@ static nufds_status_t run_output_gather(nufds_plan* p, const void* F, void* d_ou
 
 // One DFT of length L along an axis of a [rows][pitch] array without chain: a single pass from in to
 // out, or the four-step A pass into work and the B pass into out.  load_sign / store_sign apply the
-// centring factor (-1)^index on the input / output axis.
+// centring factor (-1)^index on the input / output axis; load_mul (length L, or NULL) multiplies the
+// input by a vector along the axis.
 template <typename R>
 static nufds_status_t run_transform(nufds_plan* p, const char* name_a, const char* name_b, int axis, int L, int other,
                                     int64_t pitch, int sign, const void* in, void* work, void* out, int load_sign,
-                                    int store_sign, hipStream_t s) {
+                                    int store_sign, const cpx<R>* load_mul, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     AxisPlan ap;
     if (!build_axis(axis, L, other, pitch, sign, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "transform length");
-    if (ap.single) return run_pass<R>(p, name_a, ap.passes[0], in, out, 0, load_sign, store_sign, R(1), nullptr, s);
-    NUFDS_TRY(run_pass<R>(p, name_a, ap.passes[0], in, work, 0, load_sign, 0, R(1), nullptr, s));
+    if (ap.single)
+        return run_pass<R>(p, name_a, ap.passes[0], in, out, 0, load_sign, store_sign, R(1), nullptr, s, load_mul);
+    NUFDS_TRY(run_pass<R>(p, name_a, ap.passes[0], in, work, 0, load_sign, 0, R(1), nullptr, s, load_mul));
     return run_pass<R>(p, name_b, ap.passes[1], work, out, 0, 0, store_sign, R(1), nullptr, s);
 }
 
@@ -957,9 +960,11 @@ static nufds_status_t depth_plan(nufds_plan* base, double z, const nufds_options
 
 // Steps 2-2c once (FFT of the hologram, stretch-gather, inverse DFT of the band along x then y, kept
 // in the cache), then per depth the chirp-in and the centred forward DFT of Eq. 2 and the output
-// gather.  Centring: the gather carries (-1)^k'_x and the y inverse DFT applies (-1)^k'_y on load;
-// the (-1)^(n + M/2) of each inverse DFT's output cancels against the (-1)^n of the forward DFT's
-// input (M even), which leaves (-1)^m on the forward DFT's output.
+// gather.  The chirp is separable and each axis' factor depends on that axis alone, so the x factor
+// multiplies the x transform's loads and the y factor the y transform's.  Centring: the gather
+// carries (-1)^k'_x and the y inverse DFT applies (-1)^k'_y on load; the (-1)^(n + M/2) of each
+// inverse DFT's output cancels against the (-1)^n of the forward DFT's input (M even), which leaves
+// (-1)^m on the forward DFT's output.
 template <typename R>
 static nufds_status_t run_stack(nufds_stack* S, const void* d_hologram, void* const* d_outs, hipStream_t s) {
     nufds_plan* b = S->base;
@@ -969,18 +974,17 @@ static nufds_status_t run_stack(nufds_stack* S, const void* d_hologram, void* co
     void* q = S->cache.p;
     NUFDS_TRY(run_fft1<R>(b, d_hologram, b->spec.p, w1, s));
     NUFDS_TRY(run_stretch_gather<R>(b, b->spec.p, w2, s));
-    NUFDS_TRY(run_transform<R>(b, "idft_x_a", "idft_x_b", 0, mx, my, mx, +1, w2, w1, w2, 0, 0, s));
-    NUFDS_TRY(run_transform<R>(b, "idft_y_a", "idft_y_b", 1, my, mx, mx, +1, w2, w1, q, 1, 0, s));
+    NUFDS_TRY(run_transform<R>(b, "idft_x_a", "idft_x_b", 0, mx, my, mx, +1, w2, w1, w2, 0, 0, nullptr, s));
+    NUFDS_TRY(run_transform<R>(b, "idft_y_a", "idft_y_b", 1, my, mx, mx, +1, w2, w1, q, 1, 0, nullptr, s));
     for (size_t i = 0; i < S->depth.size(); ++i) {
         nufds_plan* d = S->depth[i];
-        NUFDS_HIP_TRY(launch_chirp2d<R>(static_cast<const cpx<R>*>(q), reinterpret_cast<cpx<R>*>(w1),
-                                        static_cast<const cpx<R>*>(d->chirp_x.p),
-                                        static_cast<const cpx<R>*>(d->chirp_y.p), mx, my, s));
-        NUFDS_TRY(run_transform<R>(d, "dft_x_a", "dft_x_b", 0, mx, my, mx, -1, w1, w2, w1, 0, 1, s));
+        const cpx<R>* cxv = static_cast<const cpx<R>*>(d->chirp_x.p);
+        const cpx<R>* cyv = static_cast<const cpx<R>*>(d->chirp_y.p);
+        NUFDS_TRY(run_transform<R>(d, "dft_x_a", "dft_x_b", 0, mx, my, mx, -1, q, w2, w1, 0, 1, cxv, s));
         // only the columns this depth's output gather reads need the y transform
         const size_t coff = (size_t)d->info.fcx0 * sizeof(cpx<R>);
         NUFDS_TRY(run_transform<R>(d, "dft_y_a", "dft_y_b", 1, my, d->info.fcxn, mx, -1, w1 + coff, w2 + coff,
-                                   w1 + coff, 0, 1, s));
+                                   w1 + coff, 0, 1, cyv, s));
         NUFDS_TRY(run_output_gather<R>(d, w1, d_outs[i], s));
     }
     b->result = w1;

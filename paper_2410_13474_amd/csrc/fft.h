@@ -78,14 +78,16 @@ template <> struct OneBflyThreads<double> { static constexpr int value = 512; };
 // ---------------------------------------------------------------- loads
 
 // Source of a pass: in[offset], optionally conjugated, times (-1)^(index along the transformed axis)
-// if sign_axis, times scale.
+// if sign_axis, times scale, times mul[index along the transformed axis] if mul is set (first pass of
+// a transform only: the per-axis chirp of a cached band).
 template <typename R>
 struct LoadPlain {
     const cpx<R>* in;
     int conj;
     int sign_axis;
     R scale;
-    int plain;  // no conjugation, sign or scale: the load is a copy
+    int plain;  // no conjugation, sign, scale or multiply: the load is a copy
+    const cpx<R>* mul;
 };
 
 // ---------------------------------------------------------------- stores

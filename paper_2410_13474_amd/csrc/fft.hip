@@ -515,12 +515,19 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
                 // fused load work: conjugation, (-1)^(axis index) centring, scale (padding lanes
                 // hold finite values of valid rows; their transforms are never stored)
                 if (!ld.plain) {
-                    const int par = (j * m.an + w * m.aw + m.a0) & 1;
+                    // index along the axis (padding lanes of a partial tile take their tile's first)
+                    const int ax0 = j * m.an + (w < m.wvalid ? w : 0) * m.aw + m.a0;
+                    const int par = ax0 & 1;
 #pragma unroll
                     for (int t = 0; t < RAD; ++t) {
                         const bool flip = ld.sign_axis && ((par + t * LR * m.an) & 1);
                         const R f = flip ? -ld.scale : ld.scale;
                         v[i][t] = mk(v[i][t].x * f, (ld.conj ? -v[i][t].y : v[i][t].y) * f);
+                    }
+                    if (ld.mul) {
+#pragma unroll
+                        for (int t = 0; t < RAD; ++t)
+                            v[i][t] = v[i][t] * load_at<R>(uniform_base(ld.mul), (uint32_t)(ax0 + t * LR * m.an) * ES);
                     }
                 }
             } else {

@@ -65,11 +65,6 @@ hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, 
 template <typename R>
 hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st);
 
-// out[y][x] = in[y][x] * cx[x] * cy[y] over [my][mx] (the separable chirp-in of Eq. 2); in may be out.
-template <typename R>
-hipError_t launch_chirp2d(const cpx<R>* in, cpx<R>* out, const cpx<R>* cx, const cpx<R>* cy, int mx, int my,
-                          hipStream_t st);
-
 template <typename R>
 hipError_t launch_synth(const double* d_pts, int np, int nx, int ny, double pitch, double k, cpx<R>* out,
                         hipStream_t st);

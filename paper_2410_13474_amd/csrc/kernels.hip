@@ -396,12 +396,34 @@ template hipError_t launch_stretch_gather<double>(const GatherArgs<double>&, hip
 // FrT index q = (x' - K_c D_F) / D_F + M/2, a 4 x 4 Keys interpolation of F (zero outside the
 // FrT grid; F already carries the centring signs), times the outer chirp exp(+i k (x'^2 + y'^2) / 2z)
 // of Eq. 2 with the phase reduced mod 2 pi in float64, conjugated for diverging holograms.
+// sin and cos of a float64 phase of any magnitude, rounded to R.  complex64: Cody-Waite reduction by
+// pi/2 in float64 (two-part constant), then on [-pi/4, pi/4] the Taylor series of sin to x^9 and of
+// cos to x^10 in float32 (truncation below 2e-9, under half an ulp of 1), and the quadrant's swap and
+// signs.  complex128: reduction by 2 pi in float64 and the library sincos.
 template <typename R>
-__device__ __forceinline__ void sincos_t(R ph, R* s, R* c);
+__device__ __forceinline__ void sincos_phase(double ph, R* s, R* c);
 template <>
-__device__ __forceinline__ void sincos_t<float>(float ph, float* s, float* c) { sincosf(ph, s, c); }
+__device__ __forceinline__ void sincos_phase<float>(double ph, float* s, float* c) {
+    const double n = rint(ph * 0.63661977236758134308);  // 2 / pi
+    double r = fma(-n, 1.5707963267948966192, ph);
+    r = fma(-n, 6.1232339957367658e-17, r);
+    const float x = (float)r, x2 = x * x;
+    const float sn = fmaf(x * x2, fmaf(x2, fmaf(x2, fmaf(x2, 2.7557319e-6f, -1.9841270e-4f), 8.3333333e-3f),
+                                       -0.16666667f), x);
+    const float cs = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, -2.7557319e-7f, 2.4801587e-5f), -1.3888889e-3f),
+                                             4.1666667e-2f), -0.5f), 1.0f);
+    const int q = (int)(int64_t)n & 3;  // sin(x + q pi/2), cos(x + q pi/2)
+    float so = (q & 1) ? cs : sn, co = (q & 1) ? sn : cs;
+    *s = (q & 2) ? -so : so;
+    *c = ((q + 1) & 2) ? -co : co;
+}
 template <>
-__device__ __forceinline__ void sincos_t<double>(double ph, double* s, double* c) { sincos(ph, s, c); }
+__device__ __forceinline__ void sincos_phase<double>(double ph, double* s, double* c) {
+    const double n = rint(ph * 0.15915494309189533577);
+    ph = fma(-n, 6.283185307179586232, ph);
+    ph = fma(-n, 2.4492935982947064e-16, ph);
+    sincos(ph, s, c);
+}
 
 template <typename R>
 __global__ void output_gather_kernel(OutputArgs<R> a) {
@@ -412,13 +434,18 @@ __global__ void output_gather_kernel(OutputArgs<R> a) {
     const double y = a.cy + (double)(i - (a.sy >> 1)) * a.doy;
     double xp, yp;
     if (a.remap) {
-        // R^(-1/2) = r2^(-1/4): float seed, then two Newton steps y <- y (5 - r2 y^4) / 4 in float64
+        // R^(-1/2) = r2^(-1/4): a float seed from the square-root and reciprocal-square-root
+        // instructions (a few ulp; r2 within float's normal range), then Newton steps
+        // y <- y (5 - r2 y^4) / 4 in float64, each squaring the relative error (times 5/2): one
+        // step leaves ~2e-13 (complex64), two reach float64 rounding (complex128)
         const double r2 = x * x + y * y + a.z * a.z;
-        double t = (double)rsqrtf(sqrtf((float)r2));
+        double t = (double)__builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf((float)r2));
         double t2 = t * t;
         t = t * (5.0 - r2 * (t2 * t2)) * 0.25;
-        t2 = t * t;
-        t = t * (5.0 - r2 * (t2 * t2)) * 0.25;
+        if constexpr (sizeof(R) == 8) {
+            t2 = t * t;
+            t = t * (5.0 - r2 * (t2 * t2)) * 0.25;
+        }
         xp = a.ax[j] * t;
         yp = a.by[i] * t;
     } else {
@@ -470,13 +497,9 @@ __global__ void output_gather_kernel(OutputArgs<R> a) {
             acc = acc + racc * wb;
         }
     }
-    // outer chirp, phase in float64 reduced by a two-part 2 pi
-    double ph = (xp * xp + yp * yp) * a.kz2;
-    const double n = rint(ph * 0.15915494309189533577);
-    ph = fma(-n, 6.283185307179586232, ph);
-    ph = fma(-n, 2.4492935982947064e-16, ph);
+    // outer chirp, phase in float64
     R sn, cs;
-    sincos_t<R>(R(ph), &sn, &cs);
+    sincos_phase<R>((xp * xp + yp * yp) * a.kz2, &sn, &cs);
     cpx<R> o = acc * mk(cs, sn);
     if (a.conj_out) o.y = -o.y;
     a.out[(int64_t)i * a.sx + j] = o;
@@ -491,36 +514,6 @@ hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st) {
 }
 template hipError_t launch_output_gather<float>(const OutputArgs<float>&, hipStream_t);
 template hipError_t launch_output_gather<double>(const OutputArgs<double>&, hipStream_t);
-
-// ------------------------------------------------------------ chirp-in of a cached band
-// Multiplies the inverse DFT of the stretched band by one depth's separable chirp of Eq. 2 (each
-// axis' vector already carries 1/M): a plain streaming pass, one element per lane, rows strided over
-// the grid.
-template <typename R>
-__global__ void chirp2d_kernel(const cpx<R>* in, cpx<R>* out, const cpx<R>* __restrict__ cx,
-                               const cpx<R>* __restrict__ cy, int mx, int my) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= mx) return;
-    const cpx<R> c = cx[x];
-    for (int y = blockIdx.y; y < my; y += gridDim.y) {
-        const int64_t e = (int64_t)y * mx + x;
-        out[e] = (in[e] * c) * cy[y];
-    }
-}
-
-template <typename R>
-hipError_t launch_chirp2d(const cpx<R>* in, cpx<R>* out, const cpx<R>* cx, const cpx<R>* cy, int mx, int my,
-                          hipStream_t st) {
-    if (mx <= 0 || my <= 0) return hipSuccess;
-    dim3 block(256);
-    dim3 grid((mx + 255) / 256, my < 8192 ? my : 8192);
-    hipLaunchKernelGGL(chirp2d_kernel<R>, grid, block, 0, st, in, out, cx, cy, mx, my);
-    return hipGetLastError();
-}
-template hipError_t launch_chirp2d<float>(const cpx<float>*, cpx<float>*, const cpx<float>*, const cpx<float>*, int,
-                                          int, hipStream_t);
-template hipError_t launch_chirp2d<double>(const cpx<double>*, cpx<double>*, const cpx<double>*, const cpx<double>*,
-                                           int, int, hipStream_t);
 
 // ------------------------------------------------------------ test input
 // H[i][j] = sum_p a_p exp(i (k r + phi_p)) / r in float64, rounded to R on store.
