@@ -35,7 +35,7 @@ WORKLOADS = {
 
 PROFILE_JSON = os.path.join(ROOT, "profiles", "counters_uwa120_16k.json")
 PROFILE_MD = os.path.join(ROOT, "profiles", "nufds_kernels_uwa120_16k.md")
-OUR_KERNELS = ("fft_pass_kernel", "stretch_gather_kernel", "output_gather_kernel")
+OUR_KERNELS = ("fft_pass_kernel", "fft_fixed_kernel", "stretch_gather_kernel", "output_gather_kernel")
 
 
 def source_hash() -> str:
@@ -113,16 +113,16 @@ def summarize_profile(d):
              "bench.py reports `roofline.traffic` only while the sources still match.", "",
              "Commands (from /tmp with TMPDIR=/tmp; R = repository root, P = an output folder):", "", "```",
              "rocprofv3 --kernel-trace --stats -d $P/trace -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 5 --warmup 1 --no-cpu --no-serving --copy-calibration --roles-out $P/roles.json",
+             "--steps 5 --warmup 1 --no-cpu --no-serving --no-stack --copy-calibration --roles-out $P/roles.json",
              "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --copy-calibration",
              "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --copy-calibration",
              "python3 $R/bench.py --summarize-profile $P", "```", "",
              "## Kernel statistics (rocprofv3 --stats, complex64 and complex128 steps and plan builds)", "",
              "| kernel | calls | average ms |", "|---|---|---|"]
     for k in out["kernel_stats"]:
-        if any(x in k["kernel"] for x in OUR_KERNELS + ("map_table", "synth")):
+        if any(x in k["kernel"] for x in OUR_KERNELS + ("map_table", "tile_bounds", "synth")):
             lines.append(f"| `{k['kernel']}` | {k['calls']} | {k['avg_ms']:.3f} |")
     cal = out["calibration"]
     lines += ["", "## HBM bytes per launch (complex64 step)", "",
