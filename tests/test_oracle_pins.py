@@ -446,6 +446,53 @@ def test_focus_is_sharpest_at_the_point_depth():
     assert peaks[0.96] < peaks[0.98] < peaks[1.0] > peaks[1.02] > peaks[1.04]
 
 
+def _paper_spot(H, lam, dp, z, cx, flags=0, S=128):
+    view = dict(center_x=cx, center_y=0.0, pitch_x=0.0, pitch_y=0.0, nx=S, ny=S)
+    out, st = O.reconstruct(H, lam, dp, z, view=view, flags=flags, return_stages=True)
+    I = np.abs(out) ** 2
+    i, j = np.unravel_index(I.argmax(), I.shape)
+    xs = cx + (np.arange(S) - S // 2) * st["band"].dox
+    m = I >= 0.5 * I.max()
+    cen = float((I[m] * np.broadcast_to(xs, I.shape)[m]).sum() / I[m].sum())
+    return float(xs[j]), cen, float(I.max() / I.sum()), int(np.sum(I[i] >= 0.5 * I.max())), st["band"].dfx
+
+
+def test_fig2_at_the_papers_size():
+    """Sec. 2, Fig. 2, through the whole reconstruction at the paper's size: an 8K hologram (8192 x
+    4096, lambda = pitch = 0.5 um) of the point [0.45 B, 0, 1 m].  The plain FrT at 1 m blurs it over
+    several samples around the printed 0.461 m (Fig. 2b); at the corrected distance it is sharp at the
+    printed 0.66 m (Fig. 2e); NU-FDS at 1 m puts a sharp focus on the point itself."""
+    lam = dp = 0.5e-6
+    xo = 0.45 * O.image_size(lam, dp, 1.0)
+    pc = synth.PointCloud(np.array([xo]), np.array([0.0]), np.array([1.0]), np.array([1.0]), np.array([0.0]))
+    H = synth.point_hologram(pc, 8192, 4096, dp, lam)
+    plain = O.NO_STRETCH | O.NO_REMAP
+    _, cen, pk1, w1, _ = _paper_spot(H, lam, dp, 1.0, O.frt_spot_x(xo, 0.0, 1.0, lam), plain)
+    assert abs(cen - GOLDEN["frt_spot"]["x_ro"]) <= GOLDEN["frt_spot"]["tol"]
+    xr, zr = O.corrected_focus(xo, 0.0, 1.0, lam)
+    xp2, _, pk2, w2, _ = _paper_spot(H, lam, dp, zr, xr, plain)
+    assert abs(xp2 - GOLDEN["corrected_focus"]["x_ro"]) <= GOLDEN["corrected_focus"]["x_tol"]
+    xp3, _, pk3, w3, df = _paper_spot(H, lam, dp, 1.0, xo)
+    assert abs(xp3 - xo) <= df
+    assert w1 >= 4 and w2 <= 2 and w3 <= 2
+    assert pk3 > 3.0 * pk1 and pk2 > 3.0 * pk1
+
+
+def test_fig7_cgh2_at_the_papers_size():
+    """Sec. 5, Fig. 7b/d: CGH2 (8K, 60 deg) of P1 (0.45 B_xo, 0, 0.5 m) and P2 (0.45 B_xo - 10 mm, 0,
+    1.5 m) with B_xo = 577.4 mm: each point in focus, on its own sample, at its own depth."""
+    lam = dp = 0.5e-6
+    B = O.image_size(lam, dp, 0.5)
+    assert abs(B - GOLDEN["image_size_cgh1"]["B_m"]) <= GOLDEN["image_size_cgh1"]["B_tol"]
+    pts = ((0.45 * B, 0.5), (0.45 * B - 0.01, 1.5))
+    pc = synth.PointCloud(np.array([p[0] for p in pts]), np.zeros(2), np.array([p[1] for p in pts]),
+                          np.ones(2), np.zeros(2))
+    H = synth.point_hologram(pc, 8192, 4096, dp, lam)
+    for x, z in pts:
+        xp, _, pk, w, df = _paper_spot(H, lam, dp, z, x)
+        assert abs(xp - x) <= df and pk > 0.3 and w <= 2
+
+
 def test_focal_stack_single_depth_is_the_reconstruction():
     lam, dp, zp, xp, yp, H = _spot(90.0, 0.5, n=64, ratio=5.0)
     a = O.focal_stack(H, lam, dp, [zp])[0]
