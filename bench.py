@@ -113,11 +113,11 @@ def summarize_profile(d):
              "bench.py reports `roofline.traffic` only while the sources still match.", "",
              "Commands (from /tmp with TMPDIR=/tmp; R = repository root, P = an output folder):", "", "```",
              "rocprofv3 --kernel-trace --stats -d $P/trace -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 5 --warmup 1 --no-cpu --no-serving --no-stack --copy-calibration --roles-out $P/roles.json",
+             "--steps 5 --warmup 1 --no-cpu --no-serving --no-stack --no-oversample --copy-calibration --roles-out $P/roles.json",
              "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --copy-calibration",
              "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --copy-calibration",
              "python3 $R/bench.py --summarize-profile $P", "```", "",
              "## Kernel statistics (rocprofv3 --stats, complex64 and complex128 steps and plan builds)", "",
              "| kernel | calls | average ms |", "|---|---|---|"]
@@ -162,6 +162,7 @@ def parse():
                     help="no GPU: turn rocprofv3 output under DIR (trace/, fetch/, write/, roles.json) "
                          "into the committed summaries under profiles/")
     ap.add_argument("--no-stack", action="store_true", help="skip the focal-stack run")
+    ap.add_argument("--no-oversample", action="store_true", help="skip the oversampled-spectrum run")
     ap.add_argument("--stack-depths", default="1.0,1.2,1.4",
                     help="focal-stack depths as multiples of the workload's z")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -340,6 +341,26 @@ def serving(torch, N, n_requests, inflight=4):
                         "Poisson arrivals at 70% of closed-loop capacity"}
 
 
+def oversampled(torch, N, H, dp, n, z, steps, warmup, plain_out):
+    """The same workload with the spectrum of step 2 sampled twice as finely (complex64)."""
+    plan = N.Plan(LAM, dp, n, n, z, precision="c64", oversample=2)
+    out = torch.empty((plan.info["sy"], plan.info["sx"]), dtype=torch.complex64, device="cuda")
+    ms, launches = time_steps(plan, H, out, steps, warmup, torch)
+    kt = kernel_table(launches, steps)
+    a = out.to(torch.complex128)
+    b = plain_out.to(torch.complex128)
+    diff = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    rec = {"ms_per_step": ms, "mpix_s": plan.info["sx"] * plan.info["sy"] / (ms * 1e-3) / 1e6,
+           "workspace_gb": plan.info["workspace_bytes"] / 1e9, "rel_l2_vs_plain": diff,
+           "kernels": {k: round(v["avg_ms"], 4) for k, v in kt.items()}}
+    log(f"oversampled spectrum: {ms:.3f} ms/step, {rec['mpix_s']:.1f} Mpix/s, differs from the plain path by "
+        f"{diff:.3e} (rel L2)")
+    for name, k in sorted(kt.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches_per_step"]):
+        log(f"   {name:16s} {k['avg_ms']:8.3f} ms x{k['launches_per_step']:.0f}")
+    del plan
+    return rec
+
+
 def focal_stack(torch, N, H, dp, n, z, factors, steps, warmup, single_ms):
     """Full views at several depths from one hologram, sharing the z-independent stages (complex64)."""
     zs = [z * f for f in factors]
@@ -420,6 +441,8 @@ def main():
                          "alg_bytes_per_step": alg_bytes, "frac_hbm_end_to_end": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "info": {k: plan.info[k] for k in ("mx", "my", "kcx", "kcy", "workspace_bytes", "map_bytes")}}
         outs[prec] = out
+        if prec == "c64":
+            plain64 = out
         if args.roles_out and prec == "c64":
             per_step = len(launches) // args.steps
             with open(args.roles_out, "w") as f:
@@ -443,6 +466,11 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
+
+    over = None
+    if not args.no_oversample:
+        over = oversampled(torch, N, H64, dp, n, z, max(1, min(args.steps, 5)), args.warmup, plain64)
+    del plain64
 
     stack = None
     if not args.no_stack:
@@ -485,6 +513,7 @@ def main():
                     for p, r in results.items()},
         "partial_view_latency_ms": serve,
         "focal_stack": stack,
+        "oversampled": over,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

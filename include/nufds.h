@@ -73,6 +73,11 @@ typedef struct {
     double pad;                      /* aperture pad added to the window's x' extent, metres;
                                         < 0 selects N D / 2 per axis, 0 is the paper-literal band */
     int32_t frt_size_x, frt_size_y;  /* 0: size rule below; else a forced even 5-smooth FrT size */
+    int32_t oversample;              /* 0 or 1: the spectrum of step 2 on the hologram's own
+                                        frequency grid; 2: on a grid twice as fine (the hologram
+                                        zero-padded to 2N x 2N before its DFT), so that the Keys
+                                        interpolation of the stretch sees a spectrum sampled at twice
+                                        its critical rate */
 } nufds_options_t;
 
 /* Geometry of one reconstruction, as computed by the plan (host, float64). */
@@ -93,6 +98,7 @@ typedef struct {
     uint32_t flags;
     int32_t fcx0, fcxn;      /* FrT columns the view reads (first, count): the y transform runs on
                                 these only */
+    int32_t oversample;      /* 1 or 2: spectral grid of step 2 relative to the hologram's */
 } nufds_plan_info_t;
 
 /*

@@ -533,16 +533,21 @@ def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
     Reading: a sample is zero when f' has no pre-image on the propagating
     disk, or when the pre-image lies outside the hologram band
     |u|, |v| <= lambda / (2 Delta).
+    ``Hs`` may be the spectrum of the hologram zero-padded to sigma N (frequency
+    pitch 1 / (sigma N Delta)): the source index is then p = u sigma N Delta / lambda
+    + sigma N / 2 on that grid.
     Returns (H', u, v, valid).
     """
-    ny, nx = Hs.shape
+    nys, nxs = Hs.shape
+    nx, ny = band.nx, band.ny                 # the hologram's own grid sets f'
+    sig_x, sig_y = nxs // nx, nys // ny
     s = sine_max(wavelength, pitch)
     kgx = band.kcx + np.arange(band.mx) - band.mx // 2
     kgy = band.kcy + np.arange(band.my) - band.my // 2
     KX, KY = np.meshgrid(kgx.astype(np.float64), kgy.astype(np.float64))
     if flags & NO_STRETCH:
         # m = 1: the pre-image of spectral sample k_g is sample k_g itself.
-        px, py = KX + nx // 2, KY + ny // 2
+        px, py = sig_x * KX + nxs // 2, sig_y * KY + nys // 2
         u = KX * wavelength / (nx * pitch)
         v = KY * wavelength / (ny * pitch)
         # |u| <= s is |k_g| <= N/2 in index units; tested exactly there
@@ -552,8 +557,8 @@ def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
         vp = KY * wavelength / (ny * pitch)
         u, v, valid = inverse_stretch(up, vp)
         valid = valid & (np.abs(u) <= s) & (np.abs(v) <= s)
-        px = u * (nx * pitch / wavelength) + nx // 2
-        py = v * (ny * pitch / wavelength) + ny // 2
+        px = u * (nxs * pitch / wavelength) + nxs // 2
+        py = v * (nys * pitch / wavelength) + nys // 2
     px = np.where(valid, px, 0.0)
     py = np.where(valid, py, 0.0)
     Ht = _keys_gather(Hs, py, px, periodic=True)
@@ -586,7 +591,7 @@ def fresnel_frt(h, band: Band, wavelength, pitch, z):
 # --------------------------------------------------------------------------
 
 def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
-                frt_size=None, return_stages=False):
+                frt_size=None, return_stages=False, oversample=1):
     """NU-FDS reconstruction of hologram ``H`` at distance ``z`` (float64).
 
     ``H`` is ``[ny, nx]`` complex, pixel (i, j) at ((j - nx/2) Delta, (i - ny/2) Delta).
@@ -597,6 +602,10 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
     Eq. 3, exp(-i k R).  A hologram of diverging waves exp(+i k r)/r (the
     default) is its complex conjugate, so it is conjugated on input and the
     output is conjugated back; ``CONVERGING`` skips both.
+
+    ``oversample`` = 2 computes the spectrum of step 2 from the hologram
+    zero-padded (centred) to 2N x 2N, i.e. the same spectrum sampled twice as
+    finely, before the stretch interpolates it; everything else is unchanged.
     """
     H = np.asarray(H, dtype=np.complex128)
     ny, nx = H.shape
@@ -607,6 +616,13 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
     if not (flags & CONVERGING):
         H = np.conj(H)
     # step 2: spectrum, stretch onto the uniform f' grid, inverse transform
+    if oversample not in (1, 2):
+        raise ValueError("oversample must be 1 or 2")
+    if oversample > 1:
+        Hp = np.zeros((oversample * ny, oversample * nx), dtype=np.complex128)
+        oy, ox = (oversample - 1) * ny // 2, (oversample - 1) * nx // 2
+        Hp[oy:oy + ny, ox:ox + nx] = H
+        H = Hp
     Hs = centred_dft2(H)
     Ht, _, _, _ = stretch_gather(Hs, band, wavelength, pitch, flags)
     h = centred_idft2(Ht)

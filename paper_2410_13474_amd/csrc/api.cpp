@@ -112,8 +112,11 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
     xprime_extremes(xlo, xhi, ylo, yhi, z, remap, &xl, &xh);
     xprime_extremes(ylo, yhi, xlo, xhi, z, remap, &yl, &yh);
     double padx = 0.5 * nx * pitch, pady = 0.5 * ny * pitch;
-    int forced_x = 0, forced_y = 0;
+    int forced_x = 0, forced_y = 0, oversample = 1;
     if (opt) {
+        if (opt->oversample < 0 || opt->oversample > 2)
+            return fail(NUFDS_ERR_INVALID_ARG, "oversample must be 0, 1 or 2");
+        oversample = opt->oversample == 2 ? 2 : 1;
         if (opt->pad >= 0.0) padx = pady = opt->pad;
         forced_x = opt->frt_size_x;
         forced_y = opt->frt_size_y;
@@ -158,6 +161,7 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
     out->padx = padx;
     out->pady = pady;
     out->flags = flags;
+    out->oversample = oversample;
     // FrT columns the view reads: the taps of x' over the window (plus two samples of margin for the
     // GPU's own evaluation of the map), from a 16-column boundary; the y transform runs on these only
     if (mx > 0) {
@@ -194,10 +198,11 @@ void table_extent(double wavelength, double pitch, int nx, int ny, int* kxt, int
 }
 
 nufds_status_t check_sizes(const nufds_plan_info_t& g) {
-    if (g.mx > kMaxLen || g.my > kMaxLen || g.nx > kMaxLen || g.ny > kMaxLen || !smooth5(g.nx) || !smooth5(g.ny))
-        return fail(NUFDS_ERR_UNSUPPORTED, "sizes must be 5-smooth and at most 65536");
+    const int64_t snx = (int64_t)spectrum_factor(g) * g.nx, sny = (int64_t)spectrum_factor(g) * g.ny;
+    if (g.mx > kMaxLen || g.my > kMaxLen || snx > kMaxLen || sny > kMaxLen || !smooth5(g.nx) || !smooth5(g.ny))
+        return fail(NUFDS_ERR_UNSUPPORTED, "sizes (the oversampled spectrum's included) must be 5-smooth and at most 65536");
     const int64_t kMaxArray = (int64_t)1 << 31;  // the FFT passes index elements with 32-bit integers
-    if ((int64_t)g.nx * g.ny >= kMaxArray || (int64_t)g.mx * g.my >= kMaxArray || (int64_t)g.sx * g.sy >= kMaxArray)
+    if (snx * sny >= kMaxArray || (int64_t)g.mx * g.my >= kMaxArray || (int64_t)g.sx * g.sy >= kMaxArray)
         return fail(NUFDS_ERR_UNSUPPORTED, "hologram, FrT and output arrays must hold fewer than 2^31 elements");
     return NUFDS_OK;
 }
@@ -235,6 +240,7 @@ static void plan_free(nufds_plan* p) {
     dev_free(p->chirp_y);
     dev_free(p->ax);
     dev_free(p->by);
+    dev_free(p->hpad);
     p->twiddles.reset();
     if (p->done) (void)hipEventDestroy(p->done);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
@@ -567,8 +573,9 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* 
         a.tbx = map_tiles_x(p->kxt);
         a.tby = map_tiles_y(p->kyt);
     }
-    a.nx = g.nx;
-    a.ny = g.ny;
+    a.sigma = spectrum_factor(g);
+    a.nx = a.sigma * g.nx;  // the spectrum's grid
+    a.ny = a.sigma * g.ny;
     a.mx = g.mx;
     a.my = g.my;
     a.gx0 = g.kcx - g.mx / 2;
@@ -586,8 +593,9 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* 
     a.nty = (a.ay0 + a.nay - 1) / kGatherTile - a.ty0 + 1;
     a.nostretch = (p->flags & NUFDS_FLAG_NO_STRETCH) ? 1 : 0;
     const uint64_t es = sizeof(cpx<R>);
-    const uint64_t mm = (uint64_t)g.mx * g.my, nn = (uint64_t)g.nx * g.ny;
-    NUFDS_TRY(timing_begin(p, "stretch_gather", p->table.bytes + std::min(mm, nn) * es + mm * es, s));
+    const uint64_t mm = (uint64_t)g.mx * g.my, nn = (uint64_t)a.nx * a.ny;
+    const uint64_t sig2 = (uint64_t)a.sigma * a.sigma;
+    NUFDS_TRY(timing_begin(p, "stretch_gather", p->table.bytes + std::min(sig2 * mm, nn) * es + mm * es, s));
     NUFDS_HIP_TRY(launch_stretch_gather<R>(a, s));
     return timing_end(p, s);
 }
@@ -595,7 +603,18 @@ static nufds_status_t run_stretch_gather(nufds_plan* p, const void* spec, void* 
 template <typename R>
 nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
-    const int nx = p->info.nx, ny = p->info.ny;
+    const int sf = spectrum_factor(p->info);
+    const int nx = sf * p->info.nx, ny = sf * p->info.ny;
+    if (sf > 1) {
+        // oversampled: the hologram sits centred in the zero border of the padded array, so the
+        // centred DFT below sees the same coordinates (j - N/2) Delta on a frequency grid 1 / (2 N Delta)
+        if (!p->hpad.p) return fail(NUFDS_ERR_INVALID_ARG, "plan has no padded hologram buffer");
+        NUFDS_TRY(timing_begin(p, "pad_copy", 2ull * p->info.nx * p->info.ny * sizeof(cpx<R>), s));
+        NUFDS_HIP_TRY(launch_pad_copy<R>(static_cast<const cpx<R>*>(d_in), static_cast<cpx<R>*>(p->hpad.p),
+                                         p->info.nx, p->info.ny, nx, ny, s));
+        NUFDS_TRY(timing_end(p, s));
+        d_in = p->hpad.p;
+    }
     const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
     AxisPlan ap;
 
@@ -725,7 +744,8 @@ nufds_status_t prepare_twiddles(nufds_plan* p, bool fft1, bool band) {
     const nufds_plan_info_t& g = p->info;
     // every transform must have a pass plan; create the twiddle tables its passes read, so that
     // execute only enqueues kernels
-    const int axes[4][5] = {{0, g.nx, g.ny, g.nx, 0}, {1, g.ny, g.nx, g.nx, 0}, {0, g.mx, g.my, g.mx, 1},
+    const int snx = spectrum_factor(g) * g.nx, sny = spectrum_factor(g) * g.ny;
+    const int axes[4][5] = {{0, snx, sny, snx, 0}, {1, sny, snx, snx, 0}, {0, g.mx, g.my, g.mx, 1},
                             {1, g.my, g.fcxn, g.mx, 1}};
     for (int i = fft1 ? 0 : 2; i < (band ? 4 : 2); ++i) {
         const auto& a = axes[i];
@@ -812,12 +832,19 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     };
     hipError_t he = hipGetDevice(&p->device);
     if (he != hipSuccess) return bail(hip_fail(he, "hipGetDevice"));
-    const size_t nn = (size_t)nx * ny, mm = (size_t)g.mx * g.my;
+    const int sf = spectrum_factor(g);
+    const size_t nn = (size_t)sf * sf * nx * ny, mm = (size_t)g.mx * g.my;
     const size_t big = std::max(nn, mm);
     nufds_status_t st;
     if ((st = dev_alloc(p->spec, nn * p->esize)) != NUFDS_OK) return bail(st);
     if ((st = dev_alloc(p->work1, big * p->esize)) != NUFDS_OK) return bail(st);
     if ((st = dev_alloc(p->work2, big * p->esize)) != NUFDS_OK) return bail(st);
+    if (sf > 1) {
+        // the padded hologram: its border stays zero, each execute copies the hologram into its centre
+        if ((st = dev_alloc(p->hpad, nn * p->esize)) != NUFDS_OK) return bail(st);
+        he = hipMemset(p->hpad.p, 0, p->hpad.bytes);
+        if (he != hipSuccess) return bail(hip_fail(he, "hipMemset(padded hologram)"));
+    }
     // stretch-map table: quadrant |k_g| <= min(band extent, stretch extent) per axis
     const double s = wavelength / (2.0 * pitch);
     if (!(flags & NUFDS_FLAG_NO_STRETCH)) {
@@ -829,7 +856,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
         p->kyt = std::min(by, kmy);
         if ((st = dev_alloc(p->table, map_table_bytes(p->kxt, p->kyt))) != NUFDS_OK) return bail(st);
         he = launch_map_table(static_cast<double*>(p->table.p), p->kxt, p->kyt, wavelength, nx * pitch, ny * pitch, s,
-                              nullptr);
+                              sf, nullptr);
         if (he != hipSuccess) return bail(hip_fail(he, "map table launch"));
     }
     if ((st = upload_output_map(p)) != NUFDS_OK) return bail(st);
@@ -840,7 +867,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     he = hipDeviceSynchronize();
     if (he != hipSuccess) return bail(hip_fail(he, "plan build"));
     size_t total = p->spec.bytes + p->work1.bytes + p->work2.bytes + p->table.bytes + p->chirp_x.bytes +
-                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes;
+                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes + p->hpad.bytes;
     p->info.map_bytes = p->table.bytes;
     p->info.workspace_bytes = total;
     *out = p;
@@ -1010,6 +1037,7 @@ static nufds_status_t stack_create_impl(nufds_stack_t* out, double wavelength, d
     nufds_options_t opt;
     opt.pad = -1.0;
     opt.frt_size_x = opt.frt_size_y = 0;
+    opt.oversample = 0;
     for (int i = 0; i < n_z; ++i) {
         nufds_plan_info_t g;
         NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z[i], nullptr, flags, nullptr, &g));
@@ -1099,6 +1127,8 @@ nufds_status_t nufds_execute_spectrum(nufds_plan_t plan, nufds_spectrum_t spectr
         spectrum->wavelength != plan->wavelength || spectrum->pitch != plan->pitch ||
         (spectrum->flags & NUFDS_FLAG_CONVERGING) != (plan->flags & NUFDS_FLAG_CONVERGING))
         return fail(NUFDS_ERR_INVALID_ARG, "spectrum and plan differ in size, wavelength, pitch, precision or sign");
+    if (spectrum_factor(plan->info) != 1)
+        return fail(NUFDS_ERR_INVALID_ARG, "a cached spectrum is not oversampled; the plan is");
     return execute_common(plan, nullptr, spectrum->spec.p, d_out, static_cast<hipStream_t>(stream));
 }
 
@@ -1107,7 +1137,12 @@ nufds_status_t nufds_debug_copy(nufds_plan_t plan, int32_t which, void* d_dst, u
     const void* src = nullptr;
     uint64_t n = 0;
     switch (which) {
-        case 1: src = plan->spec.p; n = (uint64_t)plan->info.nx * plan->info.ny * plan->esize; break;
+        case 1: {
+            const uint64_t f = spectrum_factor(plan->info);
+            src = plan->spec.p;
+            n = f * f * plan->info.nx * plan->info.ny * plan->esize;
+            break;
+        }
         case 2: src = plan->result; n = (uint64_t)plan->info.mx * plan->info.my * plan->esize; break;
         case 3: src = plan->table.p; n = plan->table.p ? map_entries_bytes(plan->kxt, plan->kyt) : 0; break;
         default: return fail(NUFDS_ERR_INVALID_ARG, "unknown buffer");

@@ -40,14 +40,17 @@ struct GatherArgs {
     int ax0, ay0, nax, nay;
     int tx0, ty0, ntx, nty;
     int nostretch;
+    int sigma;            // spectral grid of the spectrum relative to the table's (1 or 2)
 };
 
 constexpr int kGatherTile = 16;
 
-// Layout of a stretch-map table: [kyt + 1][kxt + 1] float64 pairs (the pre-image of every quadrant
-// entry), then one int4 per 16 x 16 tile of entries, row-major over ceil((kxt + 1) / 16) tiles per row:
-// the least and greatest first Keys tap floor(P) - 1 over the tile's valid entries, in samples from
-// the spectrum centre, {min x, max x, min y, max y}; min x = INT_MAX for a tile with no valid entry.
+// Layout of a stretch-map table: [kyt + 1][kxt + 1] float64 pairs (the pre-image P of every quadrant
+// entry, in samples of the hologram's spectral grid), then one int4 per 16 x 16 tile of entries,
+// row-major over ceil((kxt + 1) / 16) tiles per row: the least and greatest first Keys tap
+// floor(sigma P) - 1 over the tile's valid entries on a spectral grid sigma times as fine (sigma = 1,
+// or 2 for an oversampled spectrum), in samples from the spectrum centre, {min x, max x, min y,
+// max y}; min x = INT_MAX for a tile with no valid entry.
 inline int map_tiles_x(int kxt) { return (kxt + kGatherTile) / kGatherTile; }
 inline int map_tiles_y(int kyt) { return (kyt + kGatherTile) / kGatherTile; }
 inline size_t map_entries_bytes(int kxt, int kyt) { return (size_t)(kxt + 1) * (kyt + 1) * 2 * sizeof(double); }
@@ -58,9 +61,15 @@ inline size_t map_table_bytes(int kxt, int kyt) {
 template <typename R>
 hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st);
 
-// Fills a table of map_table_bytes(kxt, kyt) bytes: the entries, then the tile bounds.
+// Fills a table of map_table_bytes(kxt, kyt) bytes: the entries, then the tile bounds for a spectrum
+// on a grid sigma times as fine as the hologram's.
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
-                            double s, hipStream_t st);
+                            double s, int sigma, hipStream_t st);
+
+// Copies the [ny][nx] hologram into the centre of the [sny][snx] zero-bordered array (rows and
+// columns offset by (sny - ny) / 2 and (snx - nx) / 2).
+template <typename R>
+hipError_t launch_pad_copy(const cpx<R>* in, cpx<R>* out, int nx, int ny, int snx, int sny, hipStream_t st);
 
 template <typename R>
 hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st);

@@ -30,10 +30,11 @@ __global__ void map_table_kernel(double* __restrict__ table, int kxt, int kyt, d
     table[2 * e + 1] = py;
 }
 
-__global__ void tile_bounds_kernel(const double* __restrict__ table, int kxt, int kyt, int4* __restrict__ bounds);
+__global__ void tile_bounds_kernel(const double* __restrict__ table, int kxt, int kyt, double sigma,
+                                   int4* __restrict__ bounds);
 
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
-                            double s, hipStream_t st) {
+                            double s, int sigma, hipStream_t st) {
     dim3 block(64, 4);
     dim3 grid((kxt + 1 + 63) / 64, (kyt + 1 + 3) / 4);
     hipLaunchKernelGGL(map_table_kernel, grid, block, 0, st, table, kxt, kyt, wavelength, npx, npy, s);
@@ -41,7 +42,7 @@ hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, 
     if (e != hipSuccess) return e;
     int4* bounds = reinterpret_cast<int4*>(reinterpret_cast<char*>(table) + map_entries_bytes(kxt, kyt));
     hipLaunchKernelGGL(tile_bounds_kernel, dim3(map_tiles_x(kxt), map_tiles_y(kyt)), dim3(kGatherTile * kGatherTile), 0,
-                       st, table, kxt, kyt, bounds);
+                       st, table, kxt, kyt, (double)sigma, bounds);
     return hipGetLastError();
 }
 
@@ -115,7 +116,7 @@ __device__ __forceinline__ cpx<R> keys_spectrum(const cpx<R>* __restrict__ spec,
 
 // Window bounds of one 16 x 16 tile of table entries (layout in kernels.h); one workgroup per tile.
 __global__ void __launch_bounds__(256) tile_bounds_kernel(const double* __restrict__ table, int kxt, int kyt,
-                                                          int4* __restrict__ bounds) {
+                                                          double sigma, int4* __restrict__ bounds) {
     constexpr int T = kGatherTile;
     __shared__ int red[4][4];
     const int tid = threadIdx.x;
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(256) tile_bounds_kernel(const double* __restri
     const int64_t e = valid ? (int64_t)ky * (kxt + 1) + kx : 0;
     const double px = table[2 * e], py = table[2 * e + 1];
     valid = valid && px == px;
-    const int fx = valid ? (int)floor(px) - 1 : 0, fy = valid ? (int)floor(py) - 1 : 0;
+    const int fx = valid ? (int)floor(sigma * px) - 1 : 0, fy = valid ? (int)floor(sigma * py) - 1 : 0;
     int r[4] = {valid ? fx : INT_MAX, valid ? -fx : INT_MAX, valid ? fy : INT_MAX, valid ? -fy : INT_MAX};
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
@@ -212,23 +213,26 @@ __global__ void __launch_bounds__(256) stretch_gather_kernel(GatherArgs<R> a) {
     bool valid;
     int bx0, bx1, by0, by1;
     if (a.nostretch) {
-        valid = inr && ax <= hx && ay <= hy;
-        px = valid ? ax : 0.0;
-        py = valid ? ay : 0.0;
-        const int lox = max(tx * T, a.ax0), hix = min(min(tx * T + T - 1, a.ax0 + a.nax - 1), hx);
-        const int loy = max(ty * T, a.ay0), hiy = min(min(ty * T + T - 1, a.ay0 + a.nay - 1), hy);
-        bx0 = (lox <= hix && loy <= hiy) ? lox - 1 : INT_MAX;
-        bx1 = hix - 1;
-        by0 = loy - 1;
-        by1 = hiy - 1;
+        // the pre-image of entry k is k itself, sigma k on the spectrum's grid
+        const int chx = hx / a.sigma, chy = hy / a.sigma;
+        valid = inr && ax <= chx && ay <= chy;
+        px = valid ? (double)(a.sigma * ax) : 0.0;
+        py = valid ? (double)(a.sigma * ay) : 0.0;
+        const int lox = max(tx * T, a.ax0), hix = min(min(tx * T + T - 1, a.ax0 + a.nax - 1), chx);
+        const int loy = max(ty * T, a.ay0), hiy = min(min(ty * T + T - 1, a.ay0 + a.nay - 1), chy);
+        bx0 = (lox <= hix && loy <= hiy) ? a.sigma * lox - 1 : INT_MAX;
+        bx1 = a.sigma * hix - 1;
+        by0 = a.sigma * loy - 1;
+        by1 = a.sigma * hiy - 1;
     } else {
         valid = inr && ax <= a.kxt && ay <= a.kyt;
         const int64_t e = valid ? (int64_t)ay * (a.kxt + 1) + ax : 0;
         const double tx_ = a.table[2 * e], ty_ = a.table[2 * e + 1];
         valid = valid && tx_ == tx_;
-        // masked entries (NaN in the table, or beyond it) never reach the index arithmetic
-        px = valid ? tx_ : 0.0;
-        py = valid ? ty_ : 0.0;
+        // masked entries (NaN in the table, or beyond it) never reach the index arithmetic; the
+        // table holds positions on the hologram's spectral grid, the spectrum may be sigma times finer
+        px = valid ? a.sigma * tx_ : 0.0;
+        py = valid ? a.sigma * ty_ : 0.0;
         bx0 = bx1 = by0 = by1 = INT_MAX;  // a tile beyond the table has no valid entry
         if (tx < a.tbx && ty < a.tby) {
             const int4 b = a.bounds[ty * a.tbx + tx];
@@ -514,6 +518,26 @@ hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st) {
 }
 template hipError_t launch_output_gather<float>(const OutputArgs<float>&, hipStream_t);
 template hipError_t launch_output_gather<double>(const OutputArgs<double>&, hipStream_t);
+
+// ------------------------------------------------------------ oversampled spectrum input
+template <typename R>
+__global__ void pad_copy_kernel(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int nx, int ny, int snx,
+                                int ox, int oy) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nx) return;
+    for (int i = blockIdx.y; i < ny; i += gridDim.y) out[(int64_t)(i + oy) * snx + (j + ox)] = in[(int64_t)i * nx + j];
+}
+
+template <typename R>
+hipError_t launch_pad_copy(const cpx<R>* in, cpx<R>* out, int nx, int ny, int snx, int sny, hipStream_t st) {
+    if (nx <= 0 || ny <= 0 || snx < nx || sny < ny) return hipErrorInvalidValue;
+    dim3 block(256);
+    dim3 grid((nx + 255) / 256, ny < 8192 ? ny : 8192);
+    hipLaunchKernelGGL(pad_copy_kernel<R>, grid, block, 0, st, in, out, nx, ny, snx, (snx - nx) / 2, (sny - ny) / 2);
+    return hipGetLastError();
+}
+template hipError_t launch_pad_copy<float>(const cpx<float>*, cpx<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_pad_copy<double>(const cpx<double>*, cpx<double>*, int, int, int, int, hipStream_t);
 
 // ------------------------------------------------------------ test input
 // H[i][j] = sum_p a_p exp(i (k r + phi_p)) / r in float64, rounded to R on store.

@@ -48,6 +48,8 @@ constexpr int kMaxLen = 65536;
 bool smooth5(int n);
 nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny, double z, const nufds_view_t* view,
                                 uint32_t flags, const nufds_options_t* opt, nufds_plan_info_t* out);
+// Spectral grid of step 2 relative to the hologram's (2 when oversampled).
+inline int spectrum_factor(const nufds_plan_info_t& g) { return g.oversample == 2 ? 2 : 1; }
 // Size limits of the kernels (5-smooth, at most kMaxLen, arrays below 2^31 elements).
 nufds_status_t check_sizes(const nufds_plan_info_t& g);
 // Largest T_1 of the stretch over the hologram band, and the quadrant table extent it implies.
@@ -68,6 +70,7 @@ struct nufds_plan {
     int device = 0;
     size_t esize = 8;
     nufds::DevBuf spec, work1, work2, table, chirp_x, chirp_y, ax, by;
+    nufds::DevBuf hpad;  // oversampled plans: the hologram zero-padded to 2N x 2N (border zeroed once)
     int kxt = -1, kyt = -1;
     std::shared_ptr<nufds::TwiddleCache> twiddles;
     hipEvent_t done = nullptr;

@@ -176,6 +176,19 @@ def test_serving_entry_points_reject_invalid_arguments():
     assert lib.nufds_server_destroy(None) == N.OK
 
 
+def test_oversample_option_geometry():
+    """The oversampling option is validated and reported on the host; the band does not change."""
+    g1 = N.plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3)
+    g2 = N.plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3, oversample=2)
+    assert g1["oversample"] == 1 and g2["oversample"] == 2
+    for k in ("mx", "my", "kcx", "kcy", "sx", "sy", "dfx", "fcx0", "fcxn"):
+        assert g1[k] == g2[k]
+    for bad in (3, -1):
+        with pytest.raises(N.NufdsError) as e:
+            N.plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3, oversample=bad)
+        assert e.value.status == N.ERR_INVALID_ARG
+
+
 def test_stack_entry_points_reject_invalid_arguments():
     """Focal-stack checks that fail before any HIP call (geometry is validated on the host)."""
     lib = N.load()

@@ -52,11 +52,12 @@ def _hologram(seed, n_points, nx, ny, fov, z_lo, z_hi):
     return dp, pc, synth.point_hologram(pc, nx, ny, dp, LAM)
 
 
-def _gpu_run(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None):
+def _gpu_run(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, oversample=None):
     _tile_cap(tile_cap)
     try:
         ny, nx = H.shape
-        plan = N.Plan(LAM, dp, nx, ny, z, view=view, precision=prec, flags=flags, pad=pad, frt_size=frt_size)
+        plan = N.Plan(LAM, dp, nx, ny, z, view=view, precision=prec, flags=flags, pad=pad, frt_size=frt_size,
+                      oversample=oversample)
     finally:
         _tile_cap(None)
     dt = torch.complex64 if prec == "c64" else torch.complex128
@@ -139,9 +140,11 @@ def test_map_table_parity(fov):
 
 # ------------------------------------------------------------- end to end
 
-def _check(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, tol=None):
-    got, plan = _gpu_run(H, dp, z, prec, view=view, flags=flags, pad=pad, frt_size=frt_size, tile_cap=tile_cap)
-    ref = O.reconstruct(_oracle_input(H, prec), LAM, dp, z, view=view, flags=flags, pad=pad, frt_size=frt_size)
+def _check(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, tol=None, oversample=None):
+    got, plan = _gpu_run(H, dp, z, prec, view=view, flags=flags, pad=pad, frt_size=frt_size, tile_cap=tile_cap,
+                         oversample=oversample)
+    ref = O.reconstruct(_oracle_input(H, prec), LAM, dp, z, view=view, flags=flags, pad=pad, frt_size=frt_size,
+                        oversample=oversample or 1)
     err = O.rel_l2(got, ref)
     say(f"   rel_l2 = {err:.3e}  (M = {plan.info['mx']} x {plan.info['my']})")
     assert err <= (tol or TOL[prec])
@@ -232,6 +235,53 @@ def test_pad_and_forced_size_parity(prec):
     z = float(pc.z[0])
     _check(H, dp, z, prec, pad=0.5 * 0.5 * n * dp)
     _check(H, dp, z, prec, frt_size=(450, 384))
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("fov", [60.0, 120.0])
+def test_oversampled_parity(prec, fov):
+    """Spectrum of the hologram zero-padded to 2N (oversample = 2): full view, a partial view, a
+    rectangular hologram, and the four-step passes of the 2N-point hologram transform."""
+    say(f"oversampled {prec} {fov}")
+    n = 256
+    dp = dp_(fov)
+    dp, pc, H = _hologram(int(fov) + 71, 5, n, n, fov, 4 * n * dp, 7 * n * dp)
+    z = float(np.median(pc.z))
+    plan = _check(H, dp, z, prec, oversample=2)
+    assert plan.info["oversample"] == 2
+    assert plan.debug_copy(1).shape == (2 * n, 2 * n)
+    B = plan.info["image_size"]
+    view = dict(center_x=0.2 * B, center_y=-0.15 * B, pitch_x=0.0, pitch_y=0.0, nx=72, ny=48)
+    _check(H, dp, z, prec, view=view, oversample=2)
+    _check(H, dp, z, prec, oversample=2, tile_cap=1024)
+    dp2, pc2, H2 = _hologram(int(fov) + 72, 4, 320, 192, fov, 4 * 320 * dp, 6 * 320 * dp)
+    _check(H2, dp2, float(np.median(pc2.z)), prec, oversample=2)
+
+
+@pytest.mark.parametrize("flags", [N.FLAG_NO_STRETCH, N.FLAG_NO_REMAP, N.FLAG_CONVERGING,
+                                   N.FLAG_NO_STRETCH | N.FLAG_NO_REMAP])
+def test_oversampled_flag_parity(flags):
+    say(f"oversampled flags {flags}")
+    n = 192
+    dp = dp_(90.0)
+    dp, pc, H = _hologram(81, 4, n, n, 90.0, 4 * n * dp, 6 * n * dp)
+    _check(H, dp, float(np.median(pc.z)), "c128", flags=flags, oversample=2)
+
+
+def test_oversampled_plan_refuses_a_cached_spectrum():
+    say("oversampled vs spectrum")
+    n = 128
+    dp = dp_(60.0)
+    dp, pc, H = _hologram(82, 2, n, n, 60.0, 4 * n * dp, 6 * n * dp)
+    Ht = torch.from_numpy(H.astype(np.complex64)).cuda()
+    plan = N.Plan(LAM, dp, n, n, float(pc.z[0]), precision="c64", oversample=2)
+    spec = N.Spectrum(Ht, LAM, dp)
+    out = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    with pytest.raises(N.NufdsError) as e:
+        plan.execute_spectrum(spec, out)
+    assert e.value.status == N.ERR_INVALID_ARG
+    spec.close()
+    plan.close()
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])

@@ -95,3 +95,17 @@ def test_stack_in_sorted_depth_order_is_caught(monkeypatch):
     _patch(monkeypatch, "focal_stack", bad_stack)
     with pytest.raises(AssertionError):
         pins.test_focal_stack_focuses_a_point_at_its_depth()
+
+
+def test_off_centre_padding_is_caught(monkeypatch):
+    good = mod.centred_dft2
+
+    def bad_dft(a):
+        # a padded array whose hologram sits one sample right of the centre: the spectrum picks up
+        # a phase ramp (the mistake an off-by-one pad offset makes)
+        if a.shape == (96, 128):
+            a = np.roll(a, 1, axis=1)
+        return good(a)
+    _patch(monkeypatch, "centred_dft2", bad_dft)
+    with pytest.raises(AssertionError):
+        pins.test_oversampled_spectrum_interleaves_the_plain_one()

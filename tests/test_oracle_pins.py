@@ -493,6 +493,54 @@ def test_fig7_cgh2_at_the_papers_size():
         assert abs(xp - x) <= df and pk > 0.3 and w <= 2
 
 
+def test_oversampled_spectrum_interleaves_the_plain_one():
+    """Zero-padding the hologram (centred) to 2N samples the same spectrum twice as finely: the even
+    samples of the padded spectrum are the plain spectrum."""
+    rng = np.random.default_rng(7)
+    H = rng.standard_normal((48, 64)) + 1j * rng.standard_normal((48, 64))
+    _, st1 = O.reconstruct(H, 0.5e-6, 0.5e-6, 1e-3, return_stages=True)
+    _, st2 = O.reconstruct(H, 0.5e-6, 0.5e-6, 1e-3, return_stages=True, oversample=2)
+    a, b = st2["spectrum"][::2, ::2], st1["spectrum"]
+    assert st2["spectrum"].shape == (96, 128)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_oversampling_without_stretch_is_the_plain_path():
+    """With the stretch off every pre-image is a spectral sample, an even sample of the finer grid,
+    where the Keys weights are (0, 1, 0, 0): oversampling changes nothing but rounding."""
+    lam, dp, zp, xp, yp, H = _spot(90.0, 0.5, n=64, ratio=5.0)
+    for flags in (O.NO_STRETCH, O.NO_STRETCH | O.NO_REMAP):
+        a = O.reconstruct(H, lam, dp, zp, flags=flags)
+        b = O.reconstruct(H, lam, dp, zp, flags=flags, oversample=2)
+        assert O.rel_l2(b, a) <= 1e-12
+
+
+def test_oversampling_brings_the_focus_closer_to_rayleigh_sommerfeld():
+    """The unpadded spectrum is critically sampled and the Keys kernel attenuates its outer samples
+    (the outer hologram aperture); sampling it twice as finely raises the normalised peak intensity of
+    a point's focus towards the brute-force Rayleigh-Sommerfeld one (measured on 128^2 holograms:
+    0.74 / 0.85 / 0.80 of RS at 60 / 90 / 120 deg without, 0.82 / 0.96 / 0.87 with)."""
+    lam = 0.5e-6
+    n, S = 128, 32
+    for fov in (60.0, 90.0, 120.0):
+        dp = synth.fov_pitch(lam, fov)
+        r1, r2 = [], []
+        for seed in range(2):
+            pc = synth.draw_points(1000 + 100 * seed + int(fov), 1, n, n, dp, lam, 4 * n * dp, 6 * n * dp)
+            H = synth.point_hologram(pc, n, n, dp, lam)
+            zp = float(pc.z[0])
+            do = lam * zp / (n * dp) / 2
+            view = dict(center_x=float(pc.x[0]), center_y=float(pc.y[0]), pitch_x=do, pitch_y=do, nx=S, ny=S)
+            X, Y = np.meshgrid(pc.x[0] + (np.arange(S) - S // 2) * do, pc.y[0] + (np.arange(S) - S // 2) * do)
+            Ir = np.abs(O.rayleigh_sommerfeld_backprop(H, dp, lam, zp, X, Y)) ** 2
+            pr = Ir.max() / Ir.sum()
+            for sig, acc in ((1, r1), (2, r2)):
+                I = np.abs(O.reconstruct(H, lam, dp, zp, view=view, oversample=sig)) ** 2
+                acc.append(I.max() / I.sum() / pr)
+        assert np.mean(r2) > np.mean(r1) + 0.03, (fov, r1, r2)
+        assert min(r2) >= 0.75
+
+
 def test_focal_stack_single_depth_is_the_reconstruction():
     lam, dp, zp, xp, yp, H = _spot(90.0, 0.5, n=64, ratio=5.0)
     a = O.focal_stack(H, lam, dp, [zp])[0]
