@@ -50,6 +50,7 @@ __all__ = [
     "keys_weight", "smooth5_even", "Band", "plan_band",
     "centred_dft2", "centred_idft2", "centred_dft2_direct",
     "stretch_gather", "fresnel_frt", "reconstruct", "focal_stack",
+    "paper_polynomial", "I_paper", "stretch_map_paper", "inverse_stretch_paper", "output_map_paper",
     "rayleigh_sommerfeld_backprop", "rel_l2",
 ]
 
@@ -275,6 +276,81 @@ def inverse_stretch(up, vp, max_iter=60):
     uu = np.where(swap, v, u) * np.sign(up)
     vv = np.where(swap, u, v) * np.sign(vp)
     return uu.reshape(shape), vv.reshape(shape), valid.reshape(shape)
+
+
+# --------------------------------------------------------------------------
+# The paper's own approximation of Eq. 16 (step 1), for comparison
+# --------------------------------------------------------------------------
+
+def paper_polynomial(s, degree=8, samples=51):
+    """Coefficients (highest power first) of the paper's stand-in for the hypergeometric function.
+
+    Sec. 4, step 1: a degree-8 polynomial fitted to 51 frequencies spread uniformly across the
+    hologram's band, whose coefficients replace 2F1 in Eq. 16.  Reading: the samples are Eq. 16 on
+    the f_x axis, m_x(f_x, 0) = 2F1(1/2, 3/4; 3/2; u^2) at u = lambda f_x in [-s, s], fitted by least
+    squares as a polynomial p(u); wherever Eq. 16 needs 2F1 at sigma^2 (sigma = u / a_v) it takes
+    p(sigma), so I(sigma) = sigma 2F1(...; sigma^2) becomes I_P(sigma) = sigma p(sigma).  Beyond the
+    fitted range (|sigma| > s, reached off the axes) the polynomial is extrapolated, as in the paper.
+    """
+    u = np.linspace(-s, s, samples)
+    return np.polyfit(u, special.hyp2f1(0.5, 0.75, 1.5, u * u), degree)
+
+
+def I_paper(sigma, coef):
+    """I_P(sigma) = sigma p(sigma) and its derivative p(sigma) + sigma p'(sigma)."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    p = np.polyval(coef, sigma)
+    dp = np.polyval(np.polyder(coef), sigma)
+    return sigma * p, p + sigma * dp
+
+
+def stretch_map_paper(u, v, coef):
+    """(u', v') = (sqrt(a_v) I_P(u / a_v), sqrt(a_u) I_P(v / a_u)): Eqs. 9-10 with the polynomial."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    av, au = np.sqrt(1.0 - v * v), np.sqrt(1.0 - u * u)
+    return np.sqrt(av) * I_paper(u / av, coef)[0], np.sqrt(au) * I_paper(v / au, coef)[0]
+
+
+def inverse_stretch_paper(up, vp, coef, iters=12):
+    """Pre-image (u, v) of (u', v') under the polynomial map, by 2-D Newton from the exact pre-image.
+
+    The two maps differ by the fit error, so the exact pre-image starts Newton within its quadratic
+    range.  Masked where the exact inverse is (no pre-image on the open disk), and where Newton
+    leaves the disk or its residual stays above 1e-13.  Returns (u, v, valid).
+    """
+    up = np.asarray(up, dtype=np.float64)
+    vp = np.asarray(vp, dtype=np.float64)
+    u, v, valid = inverse_stretch(up, vp)
+    for _ in range(iters):
+        av, au = np.sqrt(np.maximum(1.0 - v * v, 1e-300)), np.sqrt(np.maximum(1.0 - u * u, 1e-300))
+        s1, s2 = u / av, v / au
+        I1, dI1 = I_paper(s1, coef)
+        I2, dI2 = I_paper(s2, coef)
+        r1 = np.sqrt(av) * I1 - up
+        r2 = np.sqrt(au) * I2 - vp
+        # Jacobian: d sqrt(a) I(x / a) / dx = dI / sqrt(a); d / dy through a = sqrt(1 - y^2)
+        j11 = dI1 / np.sqrt(av)
+        j12 = (0.5 * I1 / np.sqrt(av) - dI1 * s1 / np.sqrt(av)) * (-v / av)
+        j22 = dI2 / np.sqrt(au)
+        j21 = (0.5 * I2 / np.sqrt(au) - dI2 * s2 / np.sqrt(au)) * (-u / au)
+        det = j11 * j22 - j12 * j21
+        du = (r1 * j22 - r2 * j12) / det
+        dv = (r2 * j11 - r1 * j21) / det
+        u = np.where(valid, u - du, u)
+        v = np.where(valid, v - dv, v)
+    r1, r2 = stretch_map_paper(u, v, coef)
+    ok = valid & (u * u + v * v < 1.0) & (np.abs(r1 - up) <= 1e-13) & (np.abs(r2 - vp) <= 1e-13)
+    return np.where(ok, u, 0.0), np.where(ok, v, 0.0), ok
+
+
+def output_map_paper(xo, yo, z, coef):
+    """Eqs. 17-18 with the polynomial: x_o' = z sqrt(a_v) I_P(u / a_v) at u = x_o / R, v = y_o / R."""
+    xo = np.asarray(xo, dtype=np.float64)
+    yo = np.asarray(yo, dtype=np.float64)
+    R = np.sqrt(xo * xo + yo * yo + z * z)
+    xp, yp = stretch_map_paper(xo / R, yo / R, coef)
+    return z * xp, z * yp
 
 
 # --------------------------------------------------------------------------
@@ -523,7 +599,7 @@ def _keys_gather(A, py, px, periodic):
     return out
 
 
-def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
+def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0, coef=None):
     """Stretched spectrum H'(f'_u) on the M_y x M_x sub-band (step 2).
 
     Sample (k'_y, k'_x) is the stretched frequency f' = (K_c + k' - M/2) / (N Delta)
@@ -535,7 +611,8 @@ def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
     |u|, |v| <= lambda / (2 Delta).
     ``Hs`` may be the spectrum of the hologram zero-padded to sigma N (frequency
     pitch 1 / (sigma N Delta)): the source index is then p = u sigma N Delta / lambda
-    + sigma N / 2 on that grid.
+    + sigma N / 2 on that grid.  ``coef``: the paper's polynomial stand-in for 2F1
+    (:func:`paper_polynomial`) instead of the exact map.
     Returns (H', u, v, valid).
     """
     nys, nxs = Hs.shape
@@ -555,7 +632,10 @@ def stretch_gather(Hs, band: Band, wavelength, pitch, flags=0):
     else:
         up = KX * wavelength / (nx * pitch)
         vp = KY * wavelength / (ny * pitch)
-        u, v, valid = inverse_stretch(up, vp)
+        if coef is None:
+            u, v, valid = inverse_stretch(up, vp)
+        else:
+            u, v, valid = inverse_stretch_paper(up, vp, coef)
         valid = valid & (np.abs(u) <= s) & (np.abs(v) <= s)
         px = u * (nxs * pitch / wavelength) + nxs // 2
         py = v * (nys * pitch / wavelength) + nys // 2
@@ -591,7 +671,7 @@ def fresnel_frt(h, band: Band, wavelength, pitch, z):
 # --------------------------------------------------------------------------
 
 def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
-                frt_size=None, return_stages=False, oversample=1):
+                frt_size=None, return_stages=False, oversample=1, map_model="exact"):
     """NU-FDS reconstruction of hologram ``H`` at distance ``z`` (float64).
 
     ``H`` is ``[ny, nx]`` complex, pixel (i, j) at ((j - nx/2) Delta, (i - ny/2) Delta).
@@ -606,12 +686,19 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
     ``oversample`` = 2 computes the spectrum of step 2 from the hologram
     zero-padded (centred) to 2N x 2N, i.e. the same spectrum sampled twice as
     finely, before the stretch interpolates it; everything else is unchanged.
+    ``map_model`` = "paper" uses the paper's polynomial stand-in for the
+    hypergeometric function (:func:`paper_polynomial`) in steps 1 and 4.
     """
     H = np.asarray(H, dtype=np.complex128)
     ny, nx = H.shape
     if nx % 2 or ny % 2:
         raise ValueError("hologram sizes must be even")
     band = plan_band(nx, ny, wavelength, pitch, z, view, flags, pad, frt_size)
+    if map_model not in ("exact", "paper"):
+        raise ValueError("map_model must be 'exact' or 'paper'")
+    # the paper variant changes steps 1 and 4 only; the band stays the exact map's (the pad covers
+    # the fit error's few-sample shift of the window's distorted image)
+    coef = paper_polynomial(sine_max(wavelength, pitch)) if map_model == "paper" else None
     k = 2.0 * math.pi / wavelength
     if not (flags & CONVERGING):
         H = np.conj(H)
@@ -624,7 +711,7 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
         Hp[oy:oy + ny, ox:ox + nx] = H
         H = Hp
     Hs = centred_dft2(H)
-    Ht, _, _, _ = stretch_gather(Hs, band, wavelength, pitch, flags)
+    Ht, _, _, _ = stretch_gather(Hs, band, wavelength, pitch, flags, coef)
     h = centred_idft2(Ht)
     # step 3: FrT
     F = fresnel_frt(h, band, wavelength, pitch, z)
@@ -636,7 +723,7 @@ def reconstruct(H, wavelength, pitch, z, view=None, flags=0, pad=None,
     if flags & NO_REMAP:
         XP, YP = XO, YO
     else:
-        XP, YP = output_map(XO, YO, z)
+        XP, YP = output_map(XO, YO, z) if coef is None else output_map_paper(XO, YO, z, coef)
     qx = (XP - band.kcx * band.dfx) / band.dfx + band.mx // 2
     qy = (YP - band.kcy * band.dfy) / band.dfy + band.my // 2
     O = _keys_gather(F, qy, qx, periodic=False)

@@ -109,3 +109,14 @@ def test_off_centre_padding_is_caught(monkeypatch):
     _patch(monkeypatch, "centred_dft2", bad_dft)
     with pytest.raises(AssertionError):
         pins.test_oversampled_spectrum_interleaves_the_plain_one()
+
+
+def test_lower_degree_paper_polynomial_is_caught(monkeypatch):
+    from scipy import special
+
+    def bad_poly(s, degree=8, samples=51):
+        u = np.linspace(-s, s, samples)
+        return np.polyfit(u, special.hyp2f1(0.5, 0.75, 1.5, u * u), 4)   # degree 4 instead of 8
+    _patch(monkeypatch, "paper_polynomial", bad_poly)
+    with pytest.raises(AssertionError):
+        pins.test_paper_polynomial_matches_eq16_where_fitted(120.0, 1e-3)

@@ -581,6 +581,59 @@ def test_fig5_wavefront_error():
         assert w2 <= w1
 
 
+@pytest.mark.parametrize("fov,bound", [(60.0, 1e-6), (90.0, 5e-5), (120.0, 1e-3)])
+def test_paper_polynomial_matches_eq16_where_fitted(fov, bound):
+    """The paper's degree-8 polynomial through 51 samples of 2F1 across the band (Sec. 4, step 1):
+    even (odd coefficients vanish), and on the f_x axis, where sigma stays within the fitted range,
+    Eq. 16 through it differs from the exact map by the fit error (2.5e-7 / 1.8e-5 / 4.8e-4)."""
+    lam = 0.5e-6
+    s = math.sin(math.radians(fov / 2))
+    c = O.paper_polynomial(s)
+    assert np.abs(c[::-1][1::2]).max() <= 1e-10
+    u = np.linspace(-s, s, 1001)
+    exact = O.stretch_map(u / lam, 0.0 * u, lam)[0] * lam
+    poly = O.stretch_map_paper(u, 0.0 * u, c)[0]
+    nz = np.abs(exact) > 1e-6
+    assert np.max(np.abs(poly - exact)[nz] / np.abs(exact[nz])) <= bound
+
+
+def test_paper_polynomial_inverse_round_trips():
+    lam = 0.5e-6
+    s = math.sin(math.radians(60.0))
+    c = O.paper_polynomial(s)
+    g = np.linspace(-0.8, 0.8, 41)
+    U, V = np.meshgrid(g, g)
+    m = U * U + V * V < 0.95
+    up, vp = O.stretch_map_paper(U[m], V[m], c)
+    u, v, ok = O.inverse_stretch_paper(up, vp, c)
+    assert ok.all()
+    assert np.abs(u - U[m]).max() <= 1e-12 and np.abs(v - V[m]).max() <= 1e-12
+
+
+def test_paper_polynomial_reconstruction():
+    """At 60 deg the polynomial is good to 3e-5 everywhere, and the reconstruction follows the exact
+    one closely; at 120 deg a point on the x axis (the paper's test points all are) still focuses on
+    its position."""
+    lam = 0.5e-6
+    lam_, dp, zp, xp, yp, H = _spot(60.0, 0.5, n=128, ratio=5.0)
+    a = O.reconstruct(H, lam, dp, zp)
+    b = O.reconstruct(H, lam, dp, zp, map_model="paper")
+    assert O.rel_l2(b, a) <= 1e-3
+    dp = synth.fov_pitch(lam, 120.0)
+    n = 256
+    zp = 8 * n * dp
+    L = 0.9 * (zp * math.tan(math.radians(60.0)) - n * dp / 2)
+    xo = 0.6 * L
+    pc = synth.PointCloud(np.array([xo]), np.array([0.0]), np.array([zp]), np.array([1.0]), np.array([0.0]))
+    H = synth.point_hologram(pc, n, n, dp, lam)
+    df = lam * zp / (n * dp)
+    S = 32
+    view = dict(center_x=xo, center_y=0.0, pitch_x=df / 4, pitch_y=df / 4, nx=S, ny=S)
+    I = np.abs(O.reconstruct(H, lam, dp, zp, view=view, map_model="paper")) ** 2
+    i, j = np.unravel_index(I.argmax(), I.shape)
+    assert abs(i - S // 2) <= 2 and abs(j - S // 2) <= 2
+
+
 def test_focal_stack_single_depth_is_the_reconstruction():
     lam, dp, zp, xp, yp, H = _spot(90.0, 0.5, n=64, ratio=5.0)
     a = O.focal_stack(H, lam, dp, [zp])[0]
