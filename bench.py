@@ -113,11 +113,11 @@ def summarize_profile(d):
              "bench.py reports `roofline.traffic` only while the sources still match.", "",
              "Commands (from /tmp with TMPDIR=/tmp; R = repository root, P = an output folder):", "", "```",
              "rocprofv3 --kernel-trace --stats -d $P/trace -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 5 --warmup 1 --no-cpu --no-serving --no-stack --no-oversample --copy-calibration --roles-out $P/roles.json",
+             "--steps 5 --warmup 1 --no-cpu --no-serving --no-stack --no-oversample --no-paper-model --copy-calibration --roles-out $P/roles.json",
              "rocprofv3 --pmc FETCH_SIZE -d $P/fetch -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --no-paper-model --copy-calibration",
              "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 $R/bench.py "
-             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --copy-calibration",
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --no-paper-model --copy-calibration",
              "python3 $R/bench.py --summarize-profile $P", "```", "",
              "## Kernel statistics (rocprofv3 --stats, complex64 and complex128 steps and plan builds)", "",
              "| kernel | calls | average ms |", "|---|---|---|"]
@@ -163,6 +163,7 @@ def parse():
                          "into the committed summaries under profiles/")
     ap.add_argument("--no-stack", action="store_true", help="skip the focal-stack run")
     ap.add_argument("--no-oversample", action="store_true", help="skip the oversampled-spectrum run")
+    ap.add_argument("--no-paper-model", action="store_true", help="skip the paper's polynomial map model run")
     ap.add_argument("--stack-depths", default="1.0,1.2,1.4",
                     help="focal-stack depths as multiples of the workload's z")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -361,6 +362,24 @@ def oversampled(torch, N, H, dp, n, z, steps, warmup, plain_out):
     return rec
 
 
+def paper_model(torch, N, H, dp, n, z, steps, warmup, exact_out):
+    """The same workload with the paper's polynomial stand-in for Eq. 16 (complex64): its time, its
+    plan build (the map table) and how far its output is from the exact map's."""
+    t0 = time.perf_counter()
+    plan = N.Plan(LAM, dp, n, n, z, precision="c64", map_model="paper")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    out = torch.empty((plan.info["sy"], plan.info["sx"]), dtype=torch.complex64, device="cuda")
+    ms, _ = time_steps(plan, H, out, steps, warmup, torch)
+    a = out.to(torch.complex128)
+    b = exact_out.to(torch.complex128)
+    diff = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    log(f"paper polynomial map model: {ms:.3f} ms/step, plan {t_plan:.2f} s, differs from the exact map's "
+        f"output by {diff:.3e} (rel L2)")
+    del plan
+    return {"ms_per_step": ms, "plan_s": t_plan, "rel_l2_vs_exact": diff}
+
+
 def focal_stack(torch, N, H, dp, n, z, factors, steps, warmup, single_ms):
     """Full views at several depths from one hologram, sharing the z-independent stages (complex64)."""
     zs = [z * f for f in factors]
@@ -470,6 +489,9 @@ def main():
     over = None
     if not args.no_oversample:
         over = oversampled(torch, N, H64, dp, n, z, max(1, min(args.steps, 5)), args.warmup, plain64)
+    pmodel = None
+    if not args.no_paper_model:
+        pmodel = paper_model(torch, N, H64, dp, n, z, max(1, min(args.steps, 5)), args.warmup, plain64)
     del plain64
 
     stack = None
@@ -514,6 +536,7 @@ def main():
         "partial_view_latency_ms": serve,
         "focal_stack": stack,
         "oversampled": over,
+        "paper_map_model": pmodel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -78,6 +78,10 @@ typedef struct {
                                         zero-padded to 2N x 2N before its DFT), so that the Keys
                                         interpolation of the stretch sees a spectrum sampled at twice
                                         its critical rate */
+    int32_t map_model;               /* 0: Eq. 16 exactly; 1: the paper's stand-in (Sec. 4, step 1),
+                                        the hypergeometric function replaced by a degree-8 polynomial
+                                        fitted by least squares to 51 samples across the band, in the
+                                        stretch (step 1) and the output map (step 4), for comparison */
 } nufds_options_t;
 
 /* Geometry of one reconstruction, as computed by the plan (host, float64). */
@@ -99,6 +103,7 @@ typedef struct {
     int32_t fcx0, fcxn;      /* FrT columns the view reads (first, count): the y transform runs on
                                 these only */
     int32_t oversample;      /* 1 or 2: spectral grid of step 2 relative to the hologram's */
+    int32_t map_model;       /* 0 exact, 1 the paper's polynomial model */
 } nufds_plan_info_t;
 
 /*

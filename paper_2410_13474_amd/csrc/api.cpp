@@ -112,10 +112,12 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
     xprime_extremes(xlo, xhi, ylo, yhi, z, remap, &xl, &xh);
     xprime_extremes(ylo, yhi, xlo, xhi, z, remap, &yl, &yh);
     double padx = 0.5 * nx * pitch, pady = 0.5 * ny * pitch;
-    int forced_x = 0, forced_y = 0, oversample = 1;
+    int forced_x = 0, forced_y = 0, oversample = 1, map_model = 0;
     if (opt) {
         if (opt->oversample < 0 || opt->oversample > 2)
             return fail(NUFDS_ERR_INVALID_ARG, "oversample must be 0, 1 or 2");
+        if (opt->map_model < 0 || opt->map_model > 1) return fail(NUFDS_ERR_INVALID_ARG, "map_model must be 0 or 1");
+        map_model = opt->map_model;
         oversample = opt->oversample == 2 ? 2 : 1;
         if (opt->pad >= 0.0) padx = pady = opt->pad;
         forced_x = opt->frt_size_x;
@@ -162,6 +164,7 @@ nufds_status_t compute_geometry(double wavelength, double pitch, int nx, int ny,
     out->pady = pady;
     out->flags = flags;
     out->oversample = oversample;
+    out->map_model = map_model;
     // FrT columns the view reads: the taps of x' over the window (plus two samples of margin for the
     // GPU's own evaluation of the map), from a 16-column boundary; the y transform runs on these only
     if (mx > 0) {
@@ -774,8 +777,12 @@ static nufds_status_t upload_output_map(nufds_plan* p) {
     if (p->flags & NUFDS_FLAG_NO_REMAP) return NUFDS_OK;
     const nufds_plan_info_t& g = p->info;
     std::vector<double> ax(g.sx), by(g.sy);
-    for (int j = 0; j < g.sx; ++j) ax[j] = output_map_factor(g.cx + (double)(j - g.sx / 2) * g.dox, p->z);
-    for (int i = 0; i < g.sy; ++i) by[i] = output_map_factor(g.cy + (double)(i - g.sy / 2) * g.doy, p->z);
+    const PaperPoly poly = paper_polynomial(p->wavelength / (2.0 * p->pitch));
+    auto factor = [&](double x) {
+        return g.map_model == 1 ? output_map_factor_paper(poly, x, p->z) : output_map_factor(x, p->z);
+    };
+    for (int j = 0; j < g.sx; ++j) ax[j] = factor(g.cx + (double)(j - g.sx / 2) * g.dox);
+    for (int i = 0; i < g.sy; ++i) by[i] = factor(g.cy + (double)(i - g.sy / 2) * g.doy);
     NUFDS_TRY(dev_alloc(p->ax, g.sx * sizeof(double)));
     NUFDS_TRY(dev_alloc(p->by, g.sy * sizeof(double)));
     NUFDS_HIP_TRY(hipMemcpy(p->ax.p, ax.data(), p->ax.bytes, hipMemcpyHostToDevice));
@@ -855,8 +862,9 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
         p->kxt = std::min(bx, kmx);
         p->kyt = std::min(by, kmy);
         if ((st = dev_alloc(p->table, map_table_bytes(p->kxt, p->kyt))) != NUFDS_OK) return bail(st);
+        const PaperPoly poly = paper_polynomial(s);
         he = launch_map_table(static_cast<double*>(p->table.p), p->kxt, p->kyt, wavelength, nx * pitch, ny * pitch, s,
-                              sf, nullptr);
+                              sf, g.map_model == 1 ? &poly : nullptr, nullptr);
         if (he != hipSuccess) return bail(hip_fail(he, "map table launch"));
     }
     if ((st = upload_output_map(p)) != NUFDS_OK) return bail(st);
@@ -1038,6 +1046,7 @@ static nufds_status_t stack_create_impl(nufds_stack_t* out, double wavelength, d
     opt.pad = -1.0;
     opt.frt_size_x = opt.frt_size_y = 0;
     opt.oversample = 0;
+    opt.map_model = 0;
     for (int i = 0; i < n_z; ++i) {
         nufds_plan_info_t g;
         NUFDS_TRY(compute_geometry(wavelength, pitch, nx, ny, z[i], nullptr, flags, nullptr, &g));

@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "fft.h"
+#include "special.h"
 
 namespace nufds {
 
@@ -62,9 +63,10 @@ template <typename R>
 hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st);
 
 // Fills a table of map_table_bytes(kxt, kyt) bytes: the entries, then the tile bounds for a spectrum
-// on a grid sigma times as fine as the hologram's.
+// on a grid sigma times as fine as the hologram's.  poly: the paper's polynomial model of Eq. 16
+// instead of the exact map (NULL: exact).
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
-                            double s, int sigma, hipStream_t st);
+                            double s, int sigma, const PaperPoly* poly, hipStream_t st);
 
 // Copies the [ny][nx] hologram into the centre of the [sny][snx] zero-bordered array (rows and
 // columns offset by (sny - ny) / 2 and (snx - nx) / 2).

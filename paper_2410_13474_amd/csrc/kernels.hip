@@ -11,9 +11,10 @@ namespace nufds {
 // Entry (ky, kx) of the quadrant table holds the pre-image, in spectral samples from the
 // centre, of the stretched frequency (kx / (N_x D), ky / (N_y D)) under Eqs. 9-10 with Eq. 16:
 // (u N_x D / lambda, v N_y D / lambda), or NaN when there is no pre-image on the propagating
-// disk or it falls outside the hologram band |u|, |v| <= lambda / (2 D).
+// disk or it falls outside the hologram band |u|, |v| <= lambda / (2 D).  With use_poly the map is
+// the paper's polynomial model (I replaced by I_P), inverted by Newton from the exact pre-image.
 __global__ void map_table_kernel(double* __restrict__ table, int kxt, int kyt, double wavelength,
-                                 double npx, double npy, double s) {
+                                 double npx, double npy, double s, PaperPoly poly, int use_poly) {
     const int kx = blockIdx.x * blockDim.x + threadIdx.x;
     const int ky = blockIdx.y * blockDim.y + threadIdx.y;
     if (kx > kxt || ky > kyt) return;
@@ -21,7 +22,8 @@ __global__ void map_table_kernel(double* __restrict__ table, int kxt, int kyt, d
     const double t2 = (double)ky * wavelength / npy;
     double u, v;
     double px = __builtin_nan(""), py = __builtin_nan("");
-    if (stretch_preimage(t1, t2, &u, &v) && u <= s && v <= s) {
+    const bool ok = use_poly ? stretch_preimage_paper(poly, t1, t2, &u, &v) : stretch_preimage(t1, t2, &u, &v);
+    if (ok && fabs(u) <= s && fabs(v) <= s) {
         px = u * (npx / wavelength);
         py = v * (npy / wavelength);
     }
@@ -34,10 +36,13 @@ __global__ void tile_bounds_kernel(const double* __restrict__ table, int kxt, in
                                    int4* __restrict__ bounds);
 
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
-                            double s, int sigma, hipStream_t st) {
+                            double s, int sigma, const PaperPoly* poly, hipStream_t st) {
     dim3 block(64, 4);
     dim3 grid((kxt + 1 + 63) / 64, (kyt + 1 + 3) / 4);
-    hipLaunchKernelGGL(map_table_kernel, grid, block, 0, st, table, kxt, kyt, wavelength, npx, npy, s);
+    PaperPoly p{};
+    if (poly) p = *poly;
+    hipLaunchKernelGGL(map_table_kernel, grid, block, 0, st, table, kxt, kyt, wavelength, npx, npy, s, p,
+                       poly ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int4* bounds = reinterpret_cast<int4*>(reinterpret_cast<char*>(table) + map_entries_bytes(kxt, kyt));

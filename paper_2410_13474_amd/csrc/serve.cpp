@@ -201,7 +201,7 @@ static nufds_status_t get_table(nufds_server* S, const nufds_spectrum* sp, hipSt
     table_extent(sp->wavelength, sp->pitch, sp->nx, sp->ny, &t->kxt, &t->kyt);
     NUFDS_TRY(dev_alloc(t->buf, map_table_bytes(t->kxt, t->kyt)));
     hipError_t e = launch_map_table(static_cast<double*>(t->buf.p), t->kxt, t->kyt, sp->wavelength,
-                                    sp->nx * sp->pitch, sp->ny * sp->pitch, sp->wavelength / (2.0 * sp->pitch), 1, s);
+                                    sp->nx * sp->pitch, sp->ny * sp->pitch, sp->wavelength / (2.0 * sp->pitch), 1, nullptr, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // other slots' streams read it next
     if (e != hipSuccess) {
         dev_free(t->buf);

@@ -164,4 +164,114 @@ NUFDS_HD double output_map_factor(double x, double z) {
     return x < 0.0 ? -a : a;
 }
 
+// ---------------------------------------------------------------- the paper's polynomial model
+// Sec. 4, step 1: the hypergeometric function of Eq. 16 replaced by a degree-8 polynomial fitted to
+// 51 frequencies spread uniformly across the band.  Read as p(u) ~ 2F1(1/2, 3/4; 3/2; u^2) on
+// u in [-s, s], used wherever Eq. 16 takes 2F1 at sigma^2, so I(sigma) becomes I_P(sigma) =
+// sigma p(sigma) (extrapolated beyond the fitted range).
+struct PaperPoly {
+    double c[9];  // p(u) = sum_k c[k] u^k
+};
+
+// Least-squares fit of the polynomial (host): 51 samples 2F1(u^2) = I(u) / u, columns (u / s)^k
+// triangularised by Householder reflections, back substitution, then rescaled to powers of u.
+inline PaperPoly paper_polynomial(double s) {
+    constexpr int NS = 51, ND = 9;
+    double A[NS][ND], b[NS];
+    for (int i = 0; i < NS; ++i) {
+        const double u = -s + 2.0 * s * i / (NS - 1);
+        const double au = std::fabs(u);
+        b[i] = au > 0.0 ? integral_i(au, std::sqrt((1.0 - au) * (1.0 + au))) / au : 1.0;
+        double x = 1.0;
+        for (int k = 0; k < ND; ++k) {
+            A[i][k] = x;
+            x *= u / s;
+        }
+    }
+    for (int k = 0; k < ND; ++k) {
+        double norm = 0.0;
+        for (int i = k; i < NS; ++i) norm += A[i][k] * A[i][k];
+        norm = std::sqrt(norm);
+        const double alpha = A[k][k] > 0.0 ? -norm : norm;
+        double v[NS];
+        for (int i = 0; i < NS; ++i) v[i] = i < k ? 0.0 : A[i][k];
+        v[k] -= alpha;
+        double vv = 0.0;
+        for (int i = k; i < NS; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        for (int j = k; j < ND; ++j) {
+            double d = 0.0;
+            for (int i = k; i < NS; ++i) d += v[i] * A[i][j];
+            d *= 2.0 / vv;
+            for (int i = k; i < NS; ++i) A[i][j] -= d * v[i];
+        }
+        double d = 0.0;
+        for (int i = k; i < NS; ++i) d += v[i] * b[i];
+        d *= 2.0 / vv;
+        for (int i = k; i < NS; ++i) b[i] -= d * v[i];
+    }
+    double x[ND];
+    for (int k = ND - 1; k >= 0; --k) {
+        double r = b[k];
+        for (int j = k + 1; j < ND; ++j) r -= A[k][j] * x[j];
+        x[k] = r / A[k][k];
+    }
+    PaperPoly P;
+    double scale = 1.0;
+    for (int k = 0; k < ND; ++k) {
+        P.c[k] = x[k] / scale;
+        scale *= s;
+    }
+    return P;
+}
+
+// I_P(sigma) = sigma p(sigma) and its derivative p(sigma) + sigma p'(sigma) (Horner).
+NUFDS_HD double paper_i(const PaperPoly& P, double sigma, double* d_out) {
+    double p = P.c[8], dp = 0.0;
+    for (int k = 7; k >= 0; --k) {
+        dp = dp * sigma + p;
+        p = p * sigma + P.c[k];
+    }
+    *d_out = p + sigma * dp;
+    return sigma * p;
+}
+
+// Pre-image under (u, v) -> (sqrt(a_v) I_P(u / a_v), sqrt(a_u) I_P(v / a_u)) by 2-D Newton from the
+// exact pre-image (the two maps differ by the fit error).  False where the exact map has no
+// pre-image, or where after the fixed 12 steps the point is off the open disk or its residual is
+// above 1e-10 (converged residuals are ~1e-16).
+NUFDS_HD bool stretch_preimage_paper(const PaperPoly& P, double t1, double t2, double* u_out, double* v_out) {
+    double u, v;
+    if (!stretch_preimage(t1, t2, &u, &v)) return false;
+    for (int it = 0; it < 12; ++it) {
+        const double av = sqrt(fmax(1.0 - v * v, 1e-300)), au = sqrt(fmax(1.0 - u * u, 1e-300));
+        const double sav = sqrt(av), sau = sqrt(au);
+        const double s1 = u / av, s2 = v / au;
+        double d1, d2;
+        const double i1 = paper_i(P, s1, &d1), i2 = paper_i(P, s2, &d2);
+        const double r1 = sav * i1 - t1, r2 = sau * i2 - t2;
+        const double j11 = d1 / sav, j22 = d2 / sau;
+        const double j12 = (0.5 * i1 / sav - d1 * s1 / sav) * (-v / av);
+        const double j21 = (0.5 * i2 / sau - d2 * s2 / sau) * (-u / au);
+        const double det = j11 * j22 - j12 * j21;
+        u -= (r1 * j22 - r2 * j12) / det;
+        v -= (r2 * j11 - r1 * j21) / det;
+    }
+    const double av = sqrt(fmax(1.0 - v * v, 1e-300)), au = sqrt(fmax(1.0 - u * u, 1e-300));
+    double d;
+    const double r1 = sqrt(av) * paper_i(P, u / av, &d) - t1;
+    const double r2 = sqrt(au) * paper_i(P, v / au, &d) - t2;
+    if (!(u * u + v * v < 1.0) || !(fabs(r1) <= 1e-10) || !(fabs(r2) <= 1e-10)) return false;
+    *u_out = u;
+    *v_out = v;
+    return true;
+}
+
+// Eqs. 17-18 with the polynomial: A_P(x) = z I_P(x / sqrt(x^2 + z^2)) (x^2 + z^2)^(1/4).
+NUFDS_HD double output_map_factor_paper(const PaperPoly& P, double x, double z) {
+    const double r = sqrt(x * x + z * z);
+    double d;
+    return z * paper_i(P, x / r, &d) * sqrt(r);
+}
+
 }  // namespace nufds

@@ -37,7 +37,7 @@ class View(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("pad", ctypes.c_double), ("frt_size_x", ctypes.c_int32), ("frt_size_y", ctypes.c_int32),
-                ("oversample", ctypes.c_int32)]
+                ("oversample", ctypes.c_int32), ("map_model", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +49,7 @@ class PlanInfo(ctypes.Structure):
                 ("ylo", ctypes.c_double), ("yhi", ctypes.c_double), ("padx", ctypes.c_double),
                 ("pady", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64), ("map_bytes", ctypes.c_uint64),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fcx0", ctypes.c_int32),
-                ("fcxn", ctypes.c_int32), ("oversample", ctypes.c_int32)]
+                ("fcxn", ctypes.c_int32), ("oversample", ctypes.c_int32), ("map_model", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -151,20 +151,24 @@ def _view(view) -> Optional[View]:
                 int(view["nx"]), int(view["ny"]))
 
 
-def _options(pad, frt_size, oversample=None) -> Optional[Options]:
-    if pad is None and frt_size is None and oversample is None:
+MAP_MODELS = {"exact": 0, "paper": 1}
+
+
+def _options(pad, frt_size, oversample=None, map_model=None) -> Optional[Options]:
+    if pad is None and frt_size is None and oversample is None and map_model is None:
         return None
     fx, fy = frt_size if frt_size is not None else (0, 0)
-    return Options(-1.0 if pad is None else float(pad), int(fx), int(fy), int(oversample or 0))
+    return Options(-1.0 if pad is None else float(pad), int(fx), int(fy), int(oversample or 0),
+                   MAP_MODELS[map_model or "exact"])
 
 
 def plan_geometry(wavelength, pitch, nx, ny, z, view=None, flags=0, pad=None, frt_size=None,
-                  oversample=None) -> dict:
+                  oversample=None, map_model=None) -> dict:
     """Host-only geometry of a plan (no GPU touched): sizes, K_c, M, pitches."""
     lib = load()
     info = PlanInfo()
     v = _view(view)
-    o = _options(pad, frt_size, oversample)
+    o = _options(pad, frt_size, oversample, map_model)
     _check(lib.nufds_plan_geometry(float(wavelength), float(pitch), int(nx), int(ny), float(z),
                                    ctypes.byref(v) if v is not None else None, int(flags),
                                    ctypes.byref(o) if o is not None else None, ctypes.byref(info)))
@@ -187,13 +191,13 @@ class Plan:
     """
 
     def __init__(self, wavelength, pitch, nx, ny, z, view=None, precision="c64", flags=0, pad=None,
-                 frt_size=None, oversample=None):
+                 frt_size=None, oversample=None, map_model=None):
         lib = load()
         self._lib = lib
         self.precision = {"c64": C64, "c128": C128}[precision]
         handle = ctypes.c_void_p()
         v = _view(view)
-        o = _options(pad, frt_size, oversample)
+        o = _options(pad, frt_size, oversample, map_model)
         vp = ctypes.byref(v) if v is not None else None
         if o is None:
             st = lib.nufds_plan_create(ctypes.byref(handle), float(wavelength), float(pitch), int(nx), int(ny),

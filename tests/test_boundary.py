@@ -187,6 +187,13 @@ def test_oversample_option_geometry():
         with pytest.raises(N.NufdsError) as e:
             N.plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3, oversample=bad)
         assert e.value.status == N.ERR_INVALID_ARG
+    g3 = N.plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3, map_model="paper")
+    assert g3["map_model"] == 1 and g1["map_model"] == 0 and g3["mx"] == g1["mx"]
+    o = N.Options(-1.0, 0, 0, 0, 2)
+    info = N.PlanInfo()
+    lib = N.load()
+    assert lib.nufds_plan_geometry(0.5e-6, 0.5e-6, 256, 192, 1e-3, None, 0, ctypes.byref(o),
+                                   ctypes.byref(info)) == N.ERR_INVALID_ARG
 
 
 def test_stack_entry_points_reject_invalid_arguments():

@@ -52,12 +52,13 @@ def _hologram(seed, n_points, nx, ny, fov, z_lo, z_hi):
     return dp, pc, synth.point_hologram(pc, nx, ny, dp, LAM)
 
 
-def _gpu_run(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, oversample=None):
+def _gpu_run(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, oversample=None,
+             map_model=None):
     _tile_cap(tile_cap)
     try:
         ny, nx = H.shape
         plan = N.Plan(LAM, dp, nx, ny, z, view=view, precision=prec, flags=flags, pad=pad, frt_size=frt_size,
-                      oversample=oversample)
+                      oversample=oversample, map_model=map_model)
     finally:
         _tile_cap(None)
     dt = torch.complex64 if prec == "c64" else torch.complex128
@@ -140,11 +141,12 @@ def test_map_table_parity(fov):
 
 # ------------------------------------------------------------- end to end
 
-def _check(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, tol=None, oversample=None):
+def _check(H, dp, z, prec, view=None, flags=0, pad=None, frt_size=None, tile_cap=None, tol=None, oversample=None,
+           map_model=None):
     got, plan = _gpu_run(H, dp, z, prec, view=view, flags=flags, pad=pad, frt_size=frt_size, tile_cap=tile_cap,
-                         oversample=oversample)
+                         oversample=oversample, map_model=map_model)
     ref = O.reconstruct(_oracle_input(H, prec), LAM, dp, z, view=view, flags=flags, pad=pad, frt_size=frt_size,
-                        oversample=oversample or 1)
+                        oversample=oversample or 1, map_model=map_model or "exact")
     err = O.rel_l2(got, ref)
     say(f"   rel_l2 = {err:.3e}  (M = {plan.info['mx']} x {plan.info['my']})")
     assert err <= (tol or TOL[prec])
@@ -256,6 +258,48 @@ def test_oversampled_parity(prec, fov):
     _check(H, dp, z, prec, oversample=2, tile_cap=1024)
     dp2, pc2, H2 = _hologram(int(fov) + 72, 4, 320, 192, fov, 4 * 320 * dp, 6 * 320 * dp)
     _check(H2, dp2, float(np.median(pc2.z)), prec, oversample=2)
+
+
+@pytest.mark.parametrize("fov", [60.0, 90.0, 120.0])
+def test_paper_map_model_table_parity(fov):
+    """The map table under the paper's polynomial model (Newton from the exact pre-image) against the
+    oracle's: the same mask, pre-images to 1e-9 samples."""
+    say(f"paper map table {fov}")
+    n = 256
+    dp = dp_(fov)
+    z = 6 * n * dp
+    plan = N.Plan(LAM, dp, n, n, z, precision="c128", map_model="paper")
+    assert plan.info["map_model"] == 1
+    tab = plan.debug_copy(3).cpu().numpy().reshape(-1, 2)
+    nxt = int(round(math.sqrt(tab.shape[0])))
+    assert nxt * nxt == tab.shape[0]
+    k = np.arange(nxt, dtype=np.float64)
+    KX, KY = np.meshgrid(k, k)
+    c = O.paper_polynomial(LAM / (2 * dp))
+    u, v, valid = O.inverse_stretch_paper(KX * LAM / (n * dp), KY * LAM / (n * dp), c)
+    s = LAM / (2 * dp)
+    valid = valid & (np.abs(u) <= s) & (np.abs(v) <= s)
+    gx = tab[:, 0].reshape(nxt, nxt)
+    gy = tab[:, 1].reshape(nxt, nxt)
+    assert np.array_equal(~np.isnan(gx), valid)
+    assert np.max(np.abs(gx[valid] - u[valid] * (n * dp / LAM))) <= 1e-9
+    assert np.max(np.abs(gy[valid] - v[valid] * (n * dp / LAM))) <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("fov", [60.0, 120.0])
+def test_paper_map_model_parity(prec, fov):
+    """Reconstruction with the paper's polynomial model of Eq. 16 (steps 1 and 4), full and partial."""
+    say(f"paper map model {prec} {fov}")
+    n = 256
+    dp = dp_(fov)
+    dp, pc, H = _hologram(int(fov) + 91, 5, n, n, fov, 4 * n * dp, 7 * n * dp)
+    z = float(np.median(pc.z))
+    _check(H, dp, z, prec, map_model="paper")
+    B = O.image_size(LAM, dp, z)
+    view = dict(center_x=-0.25 * B, center_y=0.2 * B, pitch_x=0.0, pitch_y=0.0, nx=64, ny=80)
+    _check(H, dp, z, prec, view=view, map_model="paper")
 
 
 @pytest.mark.parametrize("flags", [N.FLAG_NO_STRETCH, N.FLAG_NO_REMAP, N.FLAG_CONVERGING,
