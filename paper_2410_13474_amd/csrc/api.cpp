@@ -243,7 +243,6 @@ static void plan_free(nufds_plan* p) {
     dev_free(p->chirp_y);
     dev_free(p->ax);
     dev_free(p->by);
-    dev_free(p->hpad);
     p->twiddles.reset();
     if (p->done) (void)hipEventDestroy(p->done);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
@@ -532,7 +531,8 @@ static uint64_t pass_bytes(const PassDesc& d, size_t esize) { return 2ull * d.ro
 template <typename R>
 static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& d, const void* in, void* out,
                                int load_conj, int load_sign, int store_sign, R store_scale,
-                               const cpx<R>* chainvec, hipStream_t s, const cpx<R>* load_mul = nullptr) {
+                               const cpx<R>* chainvec, hipStream_t s, const cpx<R>* load_mul = nullptr,
+                               int win_lo = 0, int win_hi = 0) {
     const cpx<R>* tw;
     nufds_status_t st = twiddle_table<R>(p, d.L, &tw);
     if (st != NUFDS_OK) return st;
@@ -542,7 +542,7 @@ static nufds_status_t run_pass(nufds_plan* p, const char* name, const PassDesc& 
         if (st != NUFDS_OK) return st;
     }
     LoadPlain<R> ld{static_cast<const cpx<R>*>(in), load_conj, load_sign, R(1),
-                    (!load_conj && !load_sign && !load_mul) ? 1 : 0, load_mul};
+                    (!load_conj && !load_sign && !load_mul) ? 1 : 0, load_mul, win_lo, win_hi};
     StorePlain<R> sto{static_cast<cpx<R>*>(out), store_sign, store_scale, (!store_sign && store_scale == R(1)) ? 1 : 0};
     NUFDS_TRY(timing_begin(p, name, pass_bytes(d, sizeof(cpx<R>)), s));
     NUFDS_HIP_TRY((launch_pass<R>(d, ld, sto, tw, twf, chainvec, s)));
@@ -607,35 +607,40 @@ template <typename R>
 nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, hipStream_t s) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     const int sf = spectrum_factor(p->info);
-    const int nx = sf * p->info.nx, ny = sf * p->info.ny;
-    if (sf > 1) {
-        // oversampled: the hologram sits centred in the zero border of the padded array, so the
-        // centred DFT below sees the same coordinates (j - N/2) Delta on a frequency grid 1 / (2 N Delta)
-        if (!p->hpad.p) return fail(NUFDS_ERR_INVALID_ARG, "plan has no padded hologram buffer");
-        NUFDS_TRY(timing_begin(p, "pad_copy", 2ull * p->info.nx * p->info.ny * sizeof(cpx<R>), s));
-        NUFDS_HIP_TRY(launch_pad_copy<R>(static_cast<const cpx<R>*>(d_in), static_cast<cpx<R>*>(p->hpad.p),
-                                         p->info.nx, p->info.ny, nx, ny, s));
-        NUFDS_TRY(timing_end(p, s));
-        d_in = p->hpad.p;
-    }
+    const int hx = p->info.nx, hy = p->info.ny;     // hologram
+    const int nx = sf * hx, ny = sf * hy;            // spectrum
+    // oversampled: the centred DFT of the hologram zero-padded (centred) to nx x ny.  The padding is
+    // never stored: the row transforms run on the hy hologram rows only, each read as a length-nx
+    // sequence that is zero outside columns ox .. ox + hx - 1, into rows oy .. oy + hy - 1 of the
+    // spectrum; the column transforms read those rows and take the others as zero.
+    const int ox = (nx - hx) / 2, oy = (ny - hy) / 2;
+    const int xw_lo = sf > 1 ? ox : 0, xw_hi = sf > 1 ? ox + hx : 0;
+    const int yw_lo = sf > 1 ? oy : 0, yw_hi = sf > 1 ? oy + hy : 0;
+    const cpx<R>* in = static_cast<const cpx<R>*>(d_in) - ox;    // column n of a row is hologram column n - ox
+    cpx<R>* rows_out = static_cast<cpx<R>*>(spec) + (size_t)oy * nx;
     const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
     AxisPlan ap;
 
     // step 2a: centred forward DFT of the hologram, Ĥ[k] = (-1)^(k + N/2) DFT[(-1)^n H] per axis
-    if (!build_axis(0, nx, ny, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram row length");
+    if (!build_axis(0, nx, hy, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram row length");
+    ap.passes[0].in_pitch = hx;  // the first row pass reads the hologram itself
     const R sgx = ((nx / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], d_in, spec, conj_in, 1, 1, sgx, nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row", ap.passes[0], in, rows_out, conj_in, 1, 1, sgx, nullptr, s, nullptr,
+                              xw_lo, xw_hi));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], d_in, w1, conj_in, 1, 0, R(1), nullptr, s));
-        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, spec, 0, 0, 1, sgx, nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_a", ap.passes[0], in, w1, conj_in, 1, 0, R(1), nullptr, s, nullptr,
+                              xw_lo, xw_hi));
+        NUFDS_TRY(run_pass<R>(p, "fft1_row_b", ap.passes[1], w1, rows_out, 0, 0, 1, sgx, nullptr, s));
     }
     if (!build_axis(1, ny, nx, nx, -1, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "hologram column length");
     const R sgy = ((ny / 2) & 1) ? R(-1) : R(1);
     if (ap.single) {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col", ap.passes[0], spec, spec, 0, 1, 1, sgy, nullptr, s, nullptr, yw_lo,
+                              yw_hi));
     } else {
-        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, s));
+        NUFDS_TRY(run_pass<R>(p, "fft1_col_a", ap.passes[0], spec, w1, 0, 1, 0, R(1), nullptr, s, nullptr, yw_lo,
+                              yw_hi));
         NUFDS_TRY(run_pass<R>(p, "fft1_col_b", ap.passes[1], w1, spec, 0, 0, 1, sgy, nullptr, s));
     }
     return NUFDS_OK;
@@ -846,12 +851,6 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     if ((st = dev_alloc(p->spec, nn * p->esize)) != NUFDS_OK) return bail(st);
     if ((st = dev_alloc(p->work1, big * p->esize)) != NUFDS_OK) return bail(st);
     if ((st = dev_alloc(p->work2, big * p->esize)) != NUFDS_OK) return bail(st);
-    if (sf > 1) {
-        // the padded hologram: its border stays zero, each execute copies the hologram into its centre
-        if ((st = dev_alloc(p->hpad, nn * p->esize)) != NUFDS_OK) return bail(st);
-        he = hipMemset(p->hpad.p, 0, p->hpad.bytes);
-        if (he != hipSuccess) return bail(hip_fail(he, "hipMemset(padded hologram)"));
-    }
     // stretch-map table: quadrant |k_g| <= min(band extent, stretch extent) per axis
     const double s = wavelength / (2.0 * pitch);
     if (!(flags & NUFDS_FLAG_NO_STRETCH)) {
@@ -875,7 +874,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     he = hipDeviceSynchronize();
     if (he != hipSuccess) return bail(hip_fail(he, "plan build"));
     size_t total = p->spec.bytes + p->work1.bytes + p->work2.bytes + p->table.bytes + p->chirp_x.bytes +
-                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes + p->hpad.bytes;
+                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes;
     p->info.map_bytes = p->table.bytes;
     p->info.workspace_bytes = total;
     *out = p;

@@ -79,7 +79,9 @@ template <> struct OneBflyThreads<double> { static constexpr int value = 512; };
 
 // Source of a pass: in[offset], optionally conjugated, times (-1)^(index along the transformed axis)
 // if sign_axis, times scale, times mul[index along the transformed axis] if mul is set (first pass of
-// a transform only: the per-axis chirp of a cached band).
+// a transform only: the per-axis chirp of a cached band).  With win_lo < win_hi (first pass only),
+// elements whose index along the axis lies outside [win_lo, win_hi) are zero and are not read: a
+// zero-padded input held without its padding.
 template <typename R>
 struct LoadPlain {
     const cpx<R>* in;
@@ -88,6 +90,7 @@ struct LoadPlain {
     R scale;
     int plain;  // no conjugation, sign, scale or multiply: the load is a copy
     const cpx<R>* mul;
+    int win_lo, win_hi;
 };
 
 // ---------------------------------------------------------------- stores

@@ -431,7 +431,7 @@ struct StageNb {
 // w fastest for tiles of adjacent columns).  Reads of a stage all happen before the barrier that
 // precedes its LDS writes; every branch-free read uses a clamped in-bounds offset.
 template <typename R, int RAD, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN, int LC = 0,
-          int NSC = 0, int WLOG = -1>
+          int NSC = 0, int WLOG = -1, bool WIN = false>
 __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const TileMap& m, const LoadPlain<R>& ld,
                                           const StorePlain<R>& st, const ChainMul<R>& ch,
                                           const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
@@ -476,9 +476,22 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
         if (FIRST) {
             const bool valid = b0 < B && w < m.wvalid;
             const uint32_t lo = valid ? (uint32_t)(j * m.isn + w * m.isw) * ES : 0u;
+            if constexpr (WIN) {
+                // index along the axis of the element each lane reads (padding lanes read their
+                // tile's first element, whose index this is too)
+                const int ax0 = valid ? j * m.an + w * m.aw + m.a0 : m.a0;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t)
-                v[i][t] = load_at<R>(uniform_base(ld.in + ((int64_t)ib_s + (int64_t)(t * LR) * m.isn)), lo);
+                for (int t = 0; t < RAD; ++t) {
+                    const int ix = ax0 + t * LR * m.an;
+                    v[i][t] = mk(R(0), R(0));
+                    if (ix >= ld.win_lo && ix < ld.win_hi)
+                        v[i][t] = load_at<R>(uniform_base(ld.in + ((int64_t)ib_s + (int64_t)(t * LR) * m.isn)), lo);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < RAD; ++t)
+                    v[i][t] = load_at<R>(uniform_base(ld.in + ((int64_t)ib_s + (int64_t)(t * LR) * m.isn)), lo);
+            }
         } else {
 #pragma unroll
             for (int t = 0; t < RAD; ++t) v[i][t] = lds[lds_index<PAD>(((j + t * LR) << lw) + w)];
@@ -590,14 +603,15 @@ __device__ __forceinline__ void fft_stage(cpx<R>* lds, const PassDesc& d, const 
     if (!LAST) __syncthreads();
 }
 
-template <typename R, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN>
+template <typename R, int MAXE, int NBMAX, bool PAD, bool FIRST, bool LAST, bool CHAIN, int SGN, bool WIN = false>
 __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& d, const TileMap& m,
                                             const LoadPlain<R>& ld, const StorePlain<R>& st, const ChainMul<R>& ch,
                                             const cpx<R>* __restrict__ tw, const cpx<R>* __restrict__ twf, int Ns,
                                             int tid, int T) {
 #define NUFDS_STAGE(RR)                                                                             \
     if constexpr ((RR) <= MAXE)                                                                     \
-        fft_stage<R, RR, MAXE, NBMAX, PAD, FIRST, LAST, CHAIN, SGN>(lds, d, m, ld, st, ch, tw, twf, Ns, tid, T)
+        fft_stage<R, RR, MAXE, NBMAX, PAD, FIRST, LAST, CHAIN, SGN, 0, 0, -1, WIN>(lds, d, m, ld, st, ch, tw, twf, Ns, \
+                                                                                 tid, T)
     switch (r) {
         case 16: NUFDS_STAGE(16); break;
         case 8: NUFDS_STAGE(8); break;
@@ -616,7 +630,8 @@ __device__ __forceinline__ void fft_stage_r(int r, cpx<R>* lds, const PassDesc& 
 
 // NBMAX: butterflies a thread holds per stage.  NBMAX = 1 is the small-tile variant (one butterfly
 // per thread, more threads, fewer live registers); the other variant serves long single-pass rows.
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN>
+// WIN: the first stage reads through the load window of LoadPlain (non-chain passes only).
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN, bool WIN = false>
 __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R> ld, StorePlain<R> st,
                                                         const cpx<R>* __restrict__ tw,
                                                         const cpx<R>* __restrict__ twf,
@@ -648,7 +663,8 @@ __global__ void __launch_bounds__(MAXT) fft_pass_kernel(PassDesc d, LoadPlain<R>
     // transform 1: stage 0 reads global memory; the last stage writes global memory, or, in a chain
     // pass, multiplies by the chain vector (the chirp of Eq. 2) on its way to LDS
     int Ns = 1;
-#define NUFDS_RUN(F, L, C) fft_stage_r<R, MAXE, NBMAX, PAD, F, L, C, SGN>(r, lds, d, m, ld, st, ch, tw, twf, Ns, tid, T)
+#define NUFDS_RUN(F, L, C) \
+    fft_stage_r<R, MAXE, NBMAX, PAD, F, L, C, SGN, WIN && !CHAINP>(r, lds, d, m, ld, st, ch, tw, twf, Ns, tid, T)
     if constexpr (!CHAINP) {
         for (int s = 0; s < nst; ++s) {
             const int r = d.rad[s];
@@ -785,11 +801,11 @@ static bool launch_specialised(const PassDesc& d, const LoadPlain<R>& ld, const 
     return false;
 }
 
-template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN>
+template <typename R, int MAXE, int NBMAX, int MAXT, bool CHAINP, bool PAD, int SGN, bool WIN = false>
 static hipError_t launch_variant(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                                  const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     static bool attr_set = false;
-    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD, SGN>;
+    auto kern = &fft_pass_kernel<R, MAXE, NBMAX, MAXT, CHAINP, PAD, SGN, WIN>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -810,6 +826,19 @@ static hipError_t launch_signed(const PassDesc& d, const LoadPlain<R>& ld, const
     // tiles of 8 or more columns keep their lanes on consecutive LDS words without padding; the
     // several-butterflies variant serves long rows (narrow tiles) only
     const bool pad = d.W < 8;
+    if (ld.win_lo < ld.win_hi) {
+        // windowed loads: forward, non-chain passes only (the transform of a zero-padded hologram)
+        if constexpr (SG < 0) {
+            if (!d.chain) {
+                if (d.one_bfly) {
+                    if (pad) return launch_variant<R, OE, 1, OT, false, true, SG, true>(d, ld, st, tw, twf, chainvec, s);
+                    return launch_variant<R, OE, 1, OT, false, false, SG, true>(d, ld, st, tw, twf, chainvec, s);
+                }
+                return launch_variant<R, ME, 64, 1024, false, true, SG, true>(d, ld, st, tw, twf, chainvec, s);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if (d.chain) {
         if (d.one_bfly) {
             if (pad) return launch_variant<R, OE, 1, OT, true, true, SG>(d, ld, st, tw, twf, chainvec, s);
@@ -830,11 +859,12 @@ template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                        const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
     hipError_t e = hipSuccess;
+    const bool win = ld.win_lo < ld.win_hi;  // the specialised kernels read without a window
     if (d.sign < 0) {
-        if (launch_specialised<R, -1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
+        if (!win && launch_specialised<R, -1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
         return launch_signed<R, -1>(d, ld, st, tw, twf, chainvec, s);
     }
-    if (launch_specialised<R, 1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
+    if (!win && launch_specialised<R, 1>(d, ld, st, tw, twf, chainvec, s, &e)) return e;
     return launch_signed<R, 1>(d, ld, st, tw, twf, chainvec, s);
 }
 

@@ -68,11 +68,6 @@ hipError_t launch_stretch_gather(const GatherArgs<R>& a, hipStream_t st);
 hipError_t launch_map_table(double* table, int kxt, int kyt, double wavelength, double npx, double npy,
                             double s, int sigma, const PaperPoly* poly, hipStream_t st);
 
-// Copies the [ny][nx] hologram into the centre of the [sny][snx] zero-bordered array (rows and
-// columns offset by (sny - ny) / 2 and (snx - nx) / 2).
-template <typename R>
-hipError_t launch_pad_copy(const cpx<R>* in, cpx<R>* out, int nx, int ny, int snx, int sny, hipStream_t st);
-
 template <typename R>
 hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st);
 

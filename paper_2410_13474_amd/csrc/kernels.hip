@@ -524,26 +524,6 @@ hipError_t launch_output_gather(const OutputArgs<R>& a, hipStream_t st) {
 template hipError_t launch_output_gather<float>(const OutputArgs<float>&, hipStream_t);
 template hipError_t launch_output_gather<double>(const OutputArgs<double>&, hipStream_t);
 
-// ------------------------------------------------------------ oversampled spectrum input
-template <typename R>
-__global__ void pad_copy_kernel(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int nx, int ny, int snx,
-                                int ox, int oy) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nx) return;
-    for (int i = blockIdx.y; i < ny; i += gridDim.y) out[(int64_t)(i + oy) * snx + (j + ox)] = in[(int64_t)i * nx + j];
-}
-
-template <typename R>
-hipError_t launch_pad_copy(const cpx<R>* in, cpx<R>* out, int nx, int ny, int snx, int sny, hipStream_t st) {
-    if (nx <= 0 || ny <= 0 || snx < nx || sny < ny) return hipErrorInvalidValue;
-    dim3 block(256);
-    dim3 grid((nx + 255) / 256, ny < 8192 ? ny : 8192);
-    hipLaunchKernelGGL(pad_copy_kernel<R>, grid, block, 0, st, in, out, nx, ny, snx, (snx - nx) / 2, (sny - ny) / 2);
-    return hipGetLastError();
-}
-template hipError_t launch_pad_copy<float>(const cpx<float>*, cpx<float>*, int, int, int, int, hipStream_t);
-template hipError_t launch_pad_copy<double>(const cpx<double>*, cpx<double>*, int, int, int, int, hipStream_t);
-
 // ------------------------------------------------------------ test input
 // H[i][j] = sum_p a_p exp(i (k r + phi_p)) / r in float64, rounded to R on store.
 template <typename R>

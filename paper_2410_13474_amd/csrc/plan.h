@@ -70,7 +70,6 @@ struct nufds_plan {
     int device = 0;
     size_t esize = 8;
     nufds::DevBuf spec, work1, work2, table, chirp_x, chirp_y, ax, by;
-    nufds::DevBuf hpad;  // oversampled plans: the hologram zero-padded to 2N x 2N (border zeroed once)
     int kxt = -1, kyt = -1;
     std::shared_ptr<nufds::TwiddleCache> twiddles;
     hipEvent_t done = nullptr;
