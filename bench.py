@@ -35,7 +35,7 @@ WORKLOADS = {
 
 PROFILE_JSON = os.path.join(ROOT, "profiles", "counters_uwa120_16k.json")
 PROFILE_MD = os.path.join(ROOT, "profiles", "nufds_kernels_uwa120_16k.md")
-OUR_KERNELS = ("fft_pass_kernel", "fft_fixed_kernel", "stretch_gather_kernel", "output_gather_kernel")
+OUR_KERNELS = ("fft_pass_kernel", "fft_fixed_kernel", "row_chain_kernel", "stretch_gather_kernel", "output_gather_kernel")
 
 
 def source_hash() -> str:

@@ -412,6 +412,21 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
                 return true;
             }  // else more elements per thread than the registers hold: four-step
         }
+        if (chain && lim.esize == 8 && L > lim.tile_elems && row_chain_threads(L) > 0) {
+            // complex64 rows past the complex tile: the whole chain in one pass, the row in
+            // registers and its real and imaginary parts in turn through LDS
+            d.kind = K_ROWC;
+            d.L = L;
+            d.W = 1;
+            d.logW = 0;
+            d.chain = 1;
+            d.tiles_a = other;
+            d.tiles_b = 1;
+            d.nthreads = row_chain_threads(L);
+            ap->single = true;
+            ap->passes.push_back(d);
+            return true;
+        }
     } else {
         d.rows = L;
         d.cols = other;

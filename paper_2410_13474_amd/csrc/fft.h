@@ -31,7 +31,8 @@ enum PassKind : int {
     K_ROW1 = 0, K_COL1 = 1,  // whole transform in one pass
     K_ROWA = 2, K_ROWB = 3,  // four-step A and B passes along rows
     K_COLA = 4, K_COLB = 5,  // ... along columns
-    K_ROWBA = 6, K_COLBA = 7 // B pass of one transform, chain multiply, A pass of the next
+    K_ROWBA = 6, K_COLBA = 7, // B pass of one transform, chain multiply, A pass of the next
+    K_ROWC = 8                // whole chain along rows too long for a complex tile (complex64 only)
 };
 
 // LDS index of tile element i = n W + w.  Narrow tiles (PAD) insert one pad element every 32 to
@@ -122,6 +123,10 @@ hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePla
 // Radix sequence of a 5-smooth length with the fewest stages (radices 2-6, 8-10, 12, 15, 16 up to
 // max_radix); false if there is none.
 bool factor_radices(int L, int* nst, int* rad, int max_radix);
+
+// Threads of the one-pass row chain kernel for rows of L complex64 elements (rows whose complex
+// tile exceeds LDS but whose real-part plane fits), or 0 if there is no such kernel for L.
+int row_chain_threads(int L);
 
 // Whether the 32-bit per-lane offsets of the pass's global accesses can address its tiles.
 bool pass_offsets_fit(const PassDesc& d, int esize);

@@ -854,10 +854,289 @@ static hipError_t launch_signed(const PassDesc& d, const LoadPlain<R>& ld, const
 }
 
 
+// ------------------------------------------------------------ row chain in one pass
+// The chain IDFT . vec . DFT along rows whose complex64 tile exceeds LDS (25600 elements: 200 KB)
+// while a plane of their real parts fits (100 KB).  One workgroup holds one row in registers,
+// L / T elements per thread; every exchange between two stages passes through a float plane in
+// LDS twice, real parts and then imaginary parts.  The first transform's last stage and the
+// second's first stage have the same radix, so each lane already holds the elements
+// j + t L/RAD that it needs and the chain multiply takes no exchange.  Stages are the
+// Stockham stages of fft_stage: butterfly j reads x[j + t L/RAD], twiddles by
+// w_(Ns RAD)^(t k) with k = j mod Ns, and writes (j / Ns) Ns RAD + k + t Ns.
+// Butterfly j = tid + i T of a stage exists for j < L/RAD; with T a multiple of 64 a wave's
+// butterflies i either all exist or none does past the first partial wave, and waves without
+// one skip the round (wave_has); lanes past the end in a partial wave work on butterfly 0's
+// elements and store nothing.
+
+template <int A, int... REST>
+struct FirstOf {
+    static constexpr int value = A;
+};
+
+// butterflies per thread of a radix-RAD stage
+template <int L, int T, int RAD>
+struct RcNb {
+    static constexpr int value = (L / RAD + T - 1) / T;
+};
+
+// registers of a radix-RAD stage: RcNb butterflies of RAD elements
+template <int L, int T, int RAD>
+using RcRegs = cpx<float>[RcNb<L, T, RAD>::value][RAD];
+
+constexpr int rc_gcd(int a, int b) { return b == 0 ? a : rc_gcd(b, a % b); }
+
+// Plane layout of the exchange from a radix-RA stage after NSA to a radix-RB stage: one pad word
+// after every P words, P chosen so that both sides' addresses are affine in the element t of a
+// butterfly (the writer's pos = (j / NSA) NSA RA + j mod NSA + t NSA, the reader's j + t L/RB):
+// P = RA when NSA = 1 (pos / RA = j), else P divides NSA; and P divides L/RB.  The pads also
+// break the writer's strides across the LDS banks (RA + 1 words between lanes when NSA = 1).
+template <int L, int RA, int NSA, int RB>
+struct RcLayout {
+    static constexpr int LRB = L / RB;
+    static constexpr int P = NSA == 1 ? RA : rc_gcd(NSA, LRB);
+    static_assert(P >= 8 && LRB % P == 0 && (NSA == 1 || NSA % P == 0), "no affine plane layout");
+    static constexpr int wstride = NSA + NSA / P;  // writer: words between t and t + 1
+    static constexpr int rstride = LRB + LRB / P;  // reader
+};
+
+// words of the plane for every layout above (P >= 8)
+__host__ __device__ constexpr int rc_plane_words(int L) { return L + L / 8 + 1; }
+
+// whether the wave holding this thread has butterfly round i of a stage with LR butterflies
+template <int T>
+__device__ __forceinline__ bool wave_has(int wbase, int i, int LR) { return wbase + i * T < LR; }
+
+template <int L, int T, int RAD, int NS, int SGN>
+__device__ __forceinline__ void rc_butterflies(RcRegs<L, T, RAD>& v, const cpx<float>* __restrict__ tw, int tid,
+                                               int wbase) {
+    constexpr int NB = RcNb<L, T, RAD>::value;
+    constexpr int LR = L / RAD;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (!wave_has<T>(wbase, i, LR)) continue;
+        if constexpr (NS > 1) {
+            const int j0 = tid + i * T;
+            const int j = j0 < LR ? j0 : 0;
+            const int k = j % NS;
+            cpx<float> c = load_at<float>(uniform_base(tw), (uint32_t)(k * (L / (NS * RAD))) * 8u);
+            if (SGN > 0) c.y = -c.y;
+            apply_twiddles<float, RAD>(v[i], c);
+        }
+        SmallDft<float, RAD>::run(v[i], SGN);
+    }
+}
+
+// Outputs of a stage (radix RA after NSA, X_t in o[i][perm(t)]) to the inputs of a radix-RB stage.
+template <int L, int T, int RA, int NSA, int RB>
+__device__ __forceinline__ void rc_exchange(float* plane, RcRegs<L, T, RA>& o, RcRegs<L, T, RB>& u, int tid,
+                                            int wbase) {
+    using Lay = RcLayout<L, RA, NSA, RB>;
+    constexpr int NBA = RcNb<L, T, RA>::value, NBB = RcNb<L, T, RB>::value;
+    constexpr int LRA = L / RA, LRB = L / RB, P = Lay::P;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        __syncthreads();  // the previous readers of the plane are done
+        // opaque copies of the thread index: the plane addresses are recomputed in each sweep
+        // instead of being held in registers across the barriers
+        int tw_ = tid, tr_ = tid;
+        asm volatile("" : "+v"(tw_));
+#pragma unroll
+        for (int i = 0; i < NBA; ++i) {
+            const int j = tw_ + i * T;
+            if (wave_has<T>(wbase, i, LRA) && j < LRA) {
+                int a0;
+                if constexpr (NSA == 1) {
+                    a0 = j * (RA + 1);
+                } else {
+                    const int q = j / NSA, k = j - q * NSA;
+                    const int p0 = q * NSA * RA + k;
+                    a0 = p0 + p0 / P;
+                }
+#pragma unroll
+                for (int t = 0; t < RA; ++t) {
+                    const cpx<float> x = o[i][SmallDft<float, RA>::perm(t)];
+                    plane[a0 + t * Lay::wstride] = part ? x.y : x.x;
+                }
+            }
+        }
+        __syncthreads();
+        asm volatile("" : "+v"(tr_));
+#pragma unroll
+        for (int i = 0; i < NBB; ++i) {
+            if (!wave_has<T>(wbase, i, LRB)) continue;
+            const int j0 = tr_ + i * T;
+            const int j = j0 < LRB ? j0 : 0;
+            const int a0 = j + j / P;
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+                const float x = plane[a0 + t * Lay::rstride];
+                if (part) u[i][t].y = x;
+                else u[i][t].x = x;
+            }
+        }
+    }
+}
+
+// The stages of one transform, from a stage's inputs in v; fin receives the last stage's outputs
+// (X_t of butterfly j in v[i][perm(t)], at j + t L/RAD).
+template <int L, int T, int SGN, int NS, int RAD, int... RS, typename F>
+__device__ __forceinline__ void rc_stages(float* plane, RcRegs<L, T, RAD>& v, const cpx<float>* __restrict__ tw,
+                                          int tid, int wbase, F&& fin) {
+    rc_butterflies<L, T, RAD, NS, SGN>(v, tw, tid, wbase);
+    if constexpr (sizeof...(RS) == 0) {
+        static_assert(NS * RAD == L, "radices must multiply to the length");
+        fin(v);
+    } else {
+        constexpr int RB = FirstOf<RS...>::value;
+        RcRegs<L, T, RB> u;
+        rc_exchange<L, T, RAD, NS, RB>(plane, v, u, tid, wbase);
+        rc_stages<L, T, SGN, NS * RAD, RS...>(plane, u, tw, tid, wbase, fin);
+    }
+}
+
+template <int... RS>
+struct Radices {};
+
+// Row 'blockIdx.x': out = st(DFT_-SGN(vec . DFT_SGN(in))), T1 and T2 the two transforms' radices
+// (T2 opens with T1's last radix).  Loads are plain copies; the store applies the axis sign and scale.
+template <int L, int T, int SGN, int... A, int... B>
+__device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, const PassDesc& d,
+                                               const LoadPlain<float>& ld, const StorePlain<float>& st,
+                                               const cpx<float>* __restrict__ tw, const cpx<float>* __restrict__ vec,
+                                               float* plane) {
+    static_assert(T % 64 == 0, "whole waves");
+    constexpr int R0 = FirstOf<A...>::value;
+    constexpr int LR0 = L / R0;
+    const int tid = threadIdx.x;
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+    const int64_t row = blockIdx.x;
+    const cpx<float>* rin = ld.in + row * d.in_pitch;
+    cpx<float>* rout = st.out + row * d.out_pitch;
+    RcRegs<L, T, R0> v;
+#pragma unroll
+    for (int i = 0; i < RcNb<L, T, R0>::value; ++i) {
+        if (!wave_has<T>(wbase, i, LR0)) continue;
+        const int j0 = tid + i * T;
+        const int j = j0 < LR0 ? j0 : 0;
+#pragma unroll
+        for (int t = 0; t < R0; ++t) v[i][t] = load_at<float>(uniform_base(rin + t * LR0), (uint32_t)j * 8u);
+    }
+    auto store = [&](auto& o) {
+        constexpr int RL = sizeof(o[0]) / sizeof(o[0][0]);
+        constexpr int NB = sizeof(o) / sizeof(o[0]);
+        constexpr int LR = L / RL;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = tid + i * T;
+            if (wave_has<T>(wbase, i, LR) && j < LR) {
+#pragma unroll
+                for (int t = 0; t < RL; ++t) {
+                    cpx<float> x = o[i][SmallDft<float, RL>::perm(t)];
+                    if (!st.plain) {
+                        const bool flip = st.sign_axis && ((j + t * LR) & 1);
+                        const float f = flip ? -st.scale : st.scale;
+                        x = mk(x.x * f, x.y * f);
+                    }
+                    store_at<float>(uniform_base(rout + t * LR), (uint32_t)j * 8u, x);
+                }
+            }
+        }
+    };
+    auto middle = [&](auto& o) {
+        constexpr int RL = sizeof(o[0]) / sizeof(o[0][0]);
+        constexpr int NB = sizeof(o) / sizeof(o[0]);
+        constexpr int LR = L / RL;
+        static_assert(RL == FirstOf<B...>::value, "the second transform opens with the first's last radix");
+        RcRegs<L, T, RL> u;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (!wave_has<T>(wbase, i, LR)) continue;
+            const int j0 = tid + i * T;
+            const int j = j0 < LR ? j0 : 0;
+#pragma unroll
+            for (int t = 0; t < RL; ++t)
+                u[i][t] = o[i][SmallDft<float, RL>::perm(t)] *
+                          load_at<float>(uniform_base(vec), (uint32_t)(j + t * LR) * 8u);
+        }
+        rc_stages<L, T, -SGN, 1, B...>(plane, u, tw, tid, wbase, store);
+    };
+    rc_stages<L, T, SGN, 1, A...>(plane, v, tw, tid, wbase, middle);
+}
+
+// Radix plans: 25600 = 16 16 10 10 (then 10 10 16 16) over 1024 threads; 1600 = 16 10 10 over 64
+// threads, the same butterflies per thread at a length the tests reach with a lowered tile capacity.
+template <int L>
+struct RowChainPlan;
+template <>
+struct RowChainPlan<25600> {
+    static constexpr int T = 1024;
+    using A = Radices<16, 16, 10, 10>;
+    using B = Radices<10, 10, 16, 16>;
+};
+template <>
+struct RowChainPlan<1600> {
+    static constexpr int T = 64;
+    using A = Radices<16, 10, 10>;
+    using B = Radices<10, 10, 16>;
+};
+
+template <int L, int SGN>
+__global__ void __launch_bounds__(RowChainPlan<L>::T)
+    row_chain_kernel(PassDesc d, LoadPlain<float> ld, StorePlain<float> st, const cpx<float>* __restrict__ tw,
+                     const cpx<float>* __restrict__ vec) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* plane = reinterpret_cast<float*>(smem_raw);
+    using P = RowChainPlan<L>;
+    row_chain_body<L, P::T, SGN>(typename P::A{}, typename P::B{}, d, ld, st, tw, vec, plane);
+}
+
+template <int L, int SGN>
+static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& ld, const StorePlain<float>& st,
+                                     const cpx<float>* tw, const cpx<float>* vec, hipStream_t s) {
+    static bool attr_set = false;
+    auto kern = &row_chain_kernel<L, SGN>;
+    const size_t shm = (size_t)rc_plane_words(L) * sizeof(float);
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(d.rows), dim3(RowChainPlan<L>::T), shm, s, d, ld, st, tw, vec);
+    return hipGetLastError();
+}
+
+int row_chain_threads(int L) {
+    if (L == 25600) return RowChainPlan<25600>::T;
+    if (L == 1600) return RowChainPlan<1600>::T;
+    return 0;
+}
+
+template <typename R>
+static hipError_t launch_row_chain(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st,
+                                   const cpx<R>* tw, const cpx<R>* vec, hipStream_t s) {
+    if constexpr (sizeof(R) != 4) {
+        return hipErrorInvalidValue;
+    } else {
+        // plain loads only (no conjugation, sign, scale, multiply or window) and a chain vector
+        if (!ld.plain || ld.mul || ld.win_lo < ld.win_hi || !vec || d.W != 1 || d.L != d.cols ||
+            d.nthreads != row_chain_threads(d.L))
+            return hipErrorInvalidValue;
+        if (d.L == 25600)
+            return d.sign < 0 ? launch_row_chain_l<25600, -1>(d, ld, st, tw, vec, s)
+                              : launch_row_chain_l<25600, 1>(d, ld, st, tw, vec, s);
+        if (d.L == 1600)
+            return d.sign < 0 ? launch_row_chain_l<1600, -1>(d, ld, st, tw, vec, s)
+                              : launch_row_chain_l<1600, 1>(d, ld, st, tw, vec, s);
+        return hipErrorInvalidValue;
+    }
+}
+
 // The transform direction is a template parameter of the kernel (the sign folds into the butterflies).
 template <typename R>
 hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePlain<R>& st, const cpx<R>* tw,
                        const cpx<R>* twf, const cpx<R>* chainvec, hipStream_t s) {
+    if (d.kind == K_ROWC) return launch_row_chain<R>(d, ld, st, tw, chainvec, s);
     hipError_t e = hipSuccess;
     const bool win = ld.win_lo < ld.win_hi;  // the specialised kernels read without a window
     if (d.sign < 0) {
