@@ -176,8 +176,8 @@ struct TwC {
 };
 
 // R = A B with n = n2 + B n1, k = k1 + A k2: A-point DFTs over n1 in place (y[n2][k1] at v[n2 + B k1]),
-// twiddle w_R^(n2 k1), B-point DFTs over n2 in place; X_(k1 + A k2) ends in v[B k1 + k2].
-// A and B are 2, 3, 4 or 5 (identity output order).
+// twiddle w_R^(n2 k1), B-point DFTs over n2 in place; X_(k1 + A k2) ends in v[B k1 + k2].  The
+// sub-DFTs' outputs are taken back in natural order through their own perm.
 template <typename R, int A, int B>
 struct Composite {
     static constexpr int RAD = A * B;
@@ -207,7 +207,7 @@ struct Composite {
         for (int i = 0; i < A; ++i) t[i] = v[N2 + B * i];
         SmallDft<R, A>::run(t, sign);
 #pragma unroll
-        for (int i = 0; i < A; ++i) v[N2 + B * i] = t[i];
+        for (int i = 0; i < A; ++i) v[N2 + B * i] = t[SmallDft<R, A>::perm(i)];
         twiddle_row<N2>(v, sign, std::make_integer_sequence<int, A>{});
     }
     template <int N2, int... K1>
@@ -227,7 +227,7 @@ struct Composite {
             for (int i = 0; i < B; ++i) t[i] = v[B * k1 + i];
             SmallDft<R, B>::run(t, sign);
 #pragma unroll
-            for (int i = 0; i < B; ++i) v[B * k1 + i] = t[i];
+            for (int i = 0; i < B; ++i) v[B * k1 + i] = t[SmallDft<R, B>::perm(i)];
         }
     }
 };
@@ -237,6 +237,8 @@ template <typename R> struct SmallDft<R, 9> : Composite<R, 3, 3> {};
 template <typename R> struct SmallDft<R, 10> : Composite<R, 5, 2> {};
 template <typename R> struct SmallDft<R, 12> : Composite<R, 4, 3> {};
 template <typename R> struct SmallDft<R, 15> : Composite<R, 5, 3> {};
+template <typename R> struct SmallDft<R, 25> : Composite<R, 5, 5> {};  // one-pass row chains only
+template <typename R> struct SmallDft<R, 32> : Composite<R, 16, 2> {};
 
 // q = j / n for 0 <= j < 2^24 through a float reciprocal, corrected to exact.
 __device__ __forceinline__ int fdiv(int j, int n, float inv) {
@@ -1063,21 +1065,22 @@ __device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, con
     rc_stages<L, T, SGN, 1, A...>(plane, v, tw, tid, wbase, middle);
 }
 
-// Radix plans: 25600 = 16 16 10 10 (then 10 10 16 16) over 1024 threads; 1600 = 16 10 10 over 64
-// threads, the same butterflies per thread at a length the tests reach with a lowered tile capacity.
+// Radix plans: 25600 = 32 32 25 (then 25 32 32) over 1024 threads, one butterfly per thread and
+// stage; 6400 = 32 8 25 over 256 threads, the same radices and both forms of exchange at a length
+// the tests reach with a lowered tile capacity.
 template <int L>
 struct RowChainPlan;
 template <>
 struct RowChainPlan<25600> {
     static constexpr int T = 1024;
-    using A = Radices<16, 16, 10, 10>;
-    using B = Radices<10, 10, 16, 16>;
+    using A = Radices<32, 32, 25>;
+    using B = Radices<25, 32, 32>;
 };
 template <>
-struct RowChainPlan<1600> {
-    static constexpr int T = 64;
-    using A = Radices<16, 10, 10>;
-    using B = Radices<10, 10, 16>;
+struct RowChainPlan<6400> {
+    static constexpr int T = 256;
+    using A = Radices<32, 8, 25>;
+    using B = Radices<25, 8, 32>;
 };
 
 template <int L, int SGN>
@@ -1108,7 +1111,7 @@ static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& 
 
 int row_chain_threads(int L) {
     if (L == 25600) return RowChainPlan<25600>::T;
-    if (L == 1600) return RowChainPlan<1600>::T;
+    if (L == 6400) return RowChainPlan<6400>::T;
     return 0;
 }
 
@@ -1125,9 +1128,9 @@ static hipError_t launch_row_chain(const PassDesc& d, const LoadPlain<R>& ld, co
         if (d.L == 25600)
             return d.sign < 0 ? launch_row_chain_l<25600, -1>(d, ld, st, tw, vec, s)
                               : launch_row_chain_l<25600, 1>(d, ld, st, tw, vec, s);
-        if (d.L == 1600)
-            return d.sign < 0 ? launch_row_chain_l<1600, -1>(d, ld, st, tw, vec, s)
-                              : launch_row_chain_l<1600, 1>(d, ld, st, tw, vec, s);
+        if (d.L == 6400)
+            return d.sign < 0 ? launch_row_chain_l<6400, -1>(d, ld, st, tw, vec, s)
+                              : launch_row_chain_l<6400, 1>(d, ld, st, tw, vec, s);
         return hipErrorInvalidValue;
     }
 }

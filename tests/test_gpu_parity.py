@@ -344,16 +344,17 @@ def test_four_step_passes_parity(prec):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_row_chain_pass_parity(prec):
-    """FrT rows of 1600 under a 1024-element tile: complex64 runs the x chain (IDFT, chirp, DFT) in one
+    """FrT rows of 6400 under a 4096-element tile: complex64 runs the x chain (IDFT, chirp, DFT) in one
     pass with the row in registers and its real and imaginary parts exchanged through LDS in turn
-    (the kernel of the 25600-long rows of the 16384^2 workload, at the same butterflies per thread);
-    complex128 takes the four-step passes.  Full view and an off-centre partial view."""
+    (the kernel of the 25600-long rows of the 16384^2 workload, with the same radices 32 and 25 and
+    both forms of exchange); complex128 takes the four-step passes.  Full view and an off-centre
+    partial view."""
     say(f"row chain {prec}")
     n = 512
     dp = dp_(120.0)
     dp, pc, H = _hologram(93, 5, n, n, 120.0, 3 * n * dp, 5 * n * dp)
     z = float(pc.z[0])
-    plan = _check(H, dp, z, prec, frt_size=(1600, 720), tile_cap=1024)
+    plan = _check(H, dp, z, prec, frt_size=(6400, 720), tile_cap=4096)
     Ht = torch.from_numpy(H.astype(np.complex64 if prec == "c64" else np.complex128)).to("cuda")
     plan.set_timing(1)
     plan(Ht)
@@ -365,7 +366,7 @@ def test_row_chain_pass_parity(prec):
         assert "xop_a" in names and "xop" not in names
     B = O.image_size(LAM, dp, z)
     view = dict(center_x=0.21 * B, center_y=-0.13 * B, pitch_x=0.0, pitch_y=0.0, nx=200, ny=120)
-    _check(H, dp, z, prec, view=view, frt_size=(1600, 720), tile_cap=1024)
+    _check(H, dp, z, prec, view=view, frt_size=(6400, 720), tile_cap=4096)
 
 
 def test_execute_is_deterministic_and_repeatable():
