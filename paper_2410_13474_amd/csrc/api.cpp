@@ -241,6 +241,7 @@ static void plan_free(nufds_plan* p) {
     dev_free(p->table);
     dev_free(p->chirp_x);
     dev_free(p->chirp_y);
+    dev_free(p->chirp_xf);
     dev_free(p->ax);
     dev_free(p->by);
     p->twiddles.reset();
@@ -301,6 +302,31 @@ void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::
         re[n] = std::cos(ph) / M;
         im[n] = std::sin(ph) / M;
     }
+}
+
+// chirp_vector at n = j + t LR (LR = M / R, t < R) in factored form for a one-pass row transform:
+// with m = j - M/2 and D = (N pitch / M)^2 / (2 lambda z) cycles, the phase D (m + t LR)^2 is
+// D m^2 + t (2 D m LR) + t^2 (D LR^2), so c[j + t LR] = c_j a_j^t b_t with c_j = c[j],
+// a_j = exp(2 pi i 2 D m LR), b_t = exp(2 pi i D LR^2 t^2).  Output: (c_j, a_j) for j < LR, then b_t
+// for t < R; every phase in float64 reduced mod 1 cycle.
+void chirp_row_factors(int M, int N, double pitch, double wavelength, double z, int R, std::vector<double>& re,
+                       std::vector<double>& im) {
+    const int LR = M / R;
+    const double delta = N * pitch / M;
+    const double D = delta * delta / (2.0 * wavelength * z);
+    re.assign(2 * (size_t)LR + R, 0.0);
+    im.assign(2 * (size_t)LR + R, 0.0);
+    auto put = [&](size_t i, double cyc, double scale) {
+        cyc -= std::floor(cyc);
+        re[i] = std::cos(2.0 * M_PI * cyc) * scale;
+        im[i] = std::sin(2.0 * M_PI * cyc) * scale;
+    };
+    for (int j = 0; j < LR; ++j) {
+        const double m = (double)(j - M / 2);
+        put(2 * (size_t)j, D * m * m, 1.0 / M);
+        put(2 * (size_t)j + 1, 2.0 * D * m * (double)LR, 1.0);
+    }
+    for (int t = 0; t < R; ++t) put(2 * (size_t)LR + t, D * (double)LR * (double)LR * (double)t * (double)t, 1.0);
 }
 
 // ---------------------------------------------------------- pass construction
@@ -412,14 +438,14 @@ static bool build_axis(int axis, int L, int other, int64_t pitch, int sign, int 
                 return true;
             }  // else more elements per thread than the registers hold: four-step
         }
-        if (chain && lim.esize == 8 && L > lim.tile_elems && row_chain_threads(L) > 0) {
-            // complex64 rows past the complex tile: the whole chain in one pass, the row in
-            // registers and its real and imaginary parts in turn through LDS
+        if (lim.esize == 8 && L > lim.tile_elems && row_chain_threads(L) > 0) {
+            // complex64 rows past the complex tile: the whole transform (or chain) in one pass, the
+            // row in registers and its real and imaginary parts in turn through LDS
             d.kind = K_ROWC;
             d.L = L;
             d.W = 1;
             d.logW = 0;
-            d.chain = 1;
+            d.chain = chain;
             d.tiles_a = other;
             d.tiles_b = 1;
             d.nthreads = row_chain_threads(L);
@@ -703,14 +729,20 @@ static nufds_status_t run_output_gather(nufds_plan* p, const void* F, void* d_ou
 // One DFT of length L along an axis of a [rows][pitch] array without chain: a single pass from in to
 // out, or the four-step A pass into work and the B pass into out.  load_sign / store_sign apply the
 // centring factor (-1)^index on the input / output axis; load_mul (length L, or NULL) multiplies the
-// input by a vector along the axis.
+// input by a vector along the axis; load_mul_rows is the same vector in the factored form of
+// chirp_row_factors, which a one-pass row transform (K_ROWC) reads instead.
 template <typename R>
 static nufds_status_t run_transform(nufds_plan* p, const char* name_a, const char* name_b, int axis, int L, int other,
                                     int64_t pitch, int sign, const void* in, void* work, void* out, int load_sign,
-                                    int store_sign, const cpx<R>* load_mul, hipStream_t s) {
+                                    int store_sign, const cpx<R>* load_mul, hipStream_t s,
+                                    const cpx<R>* load_mul_rows = nullptr) {
     const Limits lim = limits_for(sizeof(cpx<R>), p->tile_cap, p->col_w);
     AxisPlan ap;
     if (!build_axis(axis, L, other, pitch, sign, 0, lim, &ap)) return fail(NUFDS_ERR_UNSUPPORTED, "transform length");
+    if (ap.single && ap.passes[0].kind == K_ROWC && load_mul) {
+        if (!load_mul_rows) return fail(NUFDS_ERR_UNSUPPORTED, "one-pass row transform without a factored vector");
+        load_mul = load_mul_rows;
+    }
     if (ap.single)
         return run_pass<R>(p, name_a, ap.passes[0], in, out, 0, load_sign, store_sign, R(1), nullptr, s, load_mul);
     NUFDS_TRY(run_pass<R>(p, name_a, ap.passes[0], in, work, 0, load_sign, 0, R(1), nullptr, s, load_mul));
@@ -819,6 +851,11 @@ static nufds_status_t upload_chirps(nufds_plan* p) {
     NUFDS_TRY(upload_complex<R>(p->chirp_x, re, im));
     chirp_vector(g.my, g.ny, p->pitch, p->wavelength, p->z, re, im);
     NUFDS_TRY(upload_complex<R>(p->chirp_y, re, im));
+    if (sizeof(R) == 4 && row_chain_threads(g.mx) > 0) {
+        // for x transforms that multiply the chirp on load in one pass (the focal stack's)
+        chirp_row_factors(g.mx, g.nx, p->pitch, p->wavelength, p->z, row_chain_first_radix(g.mx), re, im);
+        NUFDS_TRY(upload_complex<R>(p->chirp_xf, re, im));
+    }
     return NUFDS_OK;
 }
 
@@ -889,7 +926,7 @@ static nufds_status_t plan_create_impl(nufds_plan_t* out, double wavelength, dou
     he = hipDeviceSynchronize();
     if (he != hipSuccess) return bail(hip_fail(he, "plan build"));
     size_t total = p->spec.bytes + p->work1.bytes + p->work2.bytes + p->table.bytes + p->chirp_x.bytes +
-                   p->chirp_y.bytes + p->ax.bytes + p->by.bytes;
+                   p->chirp_y.bytes + p->chirp_xf.bytes + p->ax.bytes + p->by.bytes;
     p->info.map_bytes = p->table.bytes;
     p->info.workspace_bytes = total;
     *out = p;
@@ -1029,7 +1066,8 @@ static nufds_status_t run_stack(nufds_stack* S, const void* d_hologram, void* co
         nufds_plan* d = S->depth[i];
         const cpx<R>* cxv = static_cast<const cpx<R>*>(d->chirp_x.p);
         const cpx<R>* cyv = static_cast<const cpx<R>*>(d->chirp_y.p);
-        NUFDS_TRY(run_transform<R>(d, "dft_x_a", "dft_x_b", 0, mx, my, mx, -1, q, w2, w1, 0, 1, cxv, s));
+        NUFDS_TRY(run_transform<R>(d, "dft_x_a", "dft_x_b", 0, mx, my, mx, -1, q, w2, w1, 0, 1, cxv, s,
+                                   static_cast<const cpx<R>*>(d->chirp_xf.p)));
         // only the columns this depth's output gather reads need the y transform
         const size_t coff = (size_t)d->info.fcx0 * sizeof(cpx<R>);
         NUFDS_TRY(run_transform<R>(d, "dft_y_a", "dft_y_b", 1, my, d->info.fcxn, mx, -1, w1 + coff, w2 + coff,
@@ -1086,7 +1124,7 @@ static nufds_status_t stack_create_impl(nufds_stack_t* out, double wavelength, d
         nufds_plan* d = nullptr;
         if ((st = depth_plan(base, z[i], &opt, &d)) != NUFDS_OK) return bail(st);
         S->depth.push_back(d);
-        S->bytes += d->chirp_x.bytes + d->chirp_y.bytes + d->ax.bytes + d->by.bytes;
+        S->bytes += d->chirp_x.bytes + d->chirp_y.bytes + d->chirp_xf.bytes + d->ax.bytes + d->by.bytes;
     }
     *out = S;
     return NUFDS_OK;

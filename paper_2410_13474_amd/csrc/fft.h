@@ -2,7 +2,7 @@
 //
 // One pass transforms a tile of W independent sequences of length L held in LDS
 // (layout [n][w]); threads hold whole radix-r butterflies in registers between
-// two barriers, so a single LDS buffer serves every stage.  Eight pass kinds cover
+// two barriers, so a single LDS buffer serves every stage.  Nine pass kinds cover
 // the transforms of a row-major [rows][cols] array along either axis:
 //   ROW1 / COL1   the whole transform in one pass (rows: W consecutive rows per
 //                 tile; columns: W consecutive columns, 128-byte runs per row);
@@ -14,6 +14,9 @@
 //                 index k1 + L1 k2, and the A pass of the next transform, whose split
 //                 takes the factors in the other order (slow digit k2): one pass
 //                 instead of two for the IDFT . chirp . DFT chain.
+//   ROWC          a whole complex64 row (transform or chain) too long for a complex tile:
+//                 the row in registers, exchanged between stages through LDS as a plane of
+//                 real parts and then one of imaginary parts.
 // Loads and stores carry the fused element-wise work of the reconstruction:
 // conjugation of diverging holograms, the (-1)^n centring of the transforms, the
 // stretch-gather of step 2, and the chirp of the Fresnel transform.
@@ -32,7 +35,7 @@ enum PassKind : int {
     K_ROWA = 2, K_ROWB = 3,  // four-step A and B passes along rows
     K_COLA = 4, K_COLB = 5,  // ... along columns
     K_ROWBA = 6, K_COLBA = 7, // B pass of one transform, chain multiply, A pass of the next
-    K_ROWC = 8                // whole chain along rows too long for a complex tile (complex64 only)
+    K_ROWC = 8                // whole transform or chain along rows too long for a complex tile (complex64)
 };
 
 // LDS index of tile element i = n W + w.  Narrow tiles (PAD) insert one pad element every 32 to
@@ -82,7 +85,9 @@ template <> struct OneBflyThreads<double> { static constexpr int value = 512; };
 // if sign_axis, times scale, times mul[index along the transformed axis] if mul is set (first pass of
 // a transform only: the per-axis chirp of a cached band).  With win_lo < win_hi (first pass only),
 // elements whose index along the axis lies outside [win_lo, win_hi) are zero and are not read: a
-// zero-padded input held without its padding.
+// zero-padded input held without its padding.  In a one-pass row transform (K_ROWC, not a chain)
+// mul holds the vector in factored form: for the first-stage radix R and LR = L/R, the pairs
+// (c_j, a_j), j < LR, then b_t, t < R, with mul[j + t LR] = c_j a_j^t b_t (a chirp factors so).
 template <typename R>
 struct LoadPlain {
     const cpx<R>* in;
@@ -124,9 +129,11 @@ hipError_t launch_pass(const PassDesc& d, const LoadPlain<R>& ld, const StorePla
 // max_radix); false if there is none.
 bool factor_radices(int L, int* nst, int* rad, int max_radix);
 
-// Threads of the one-pass row chain kernel for rows of L complex64 elements (rows whose complex
-// tile exceeds LDS but whose real-part plane fits), or 0 if there is no such kernel for L.
+// Threads of the one-pass row kernel (a transform or a chain) for rows of L complex64 elements
+// (rows whose complex tile exceeds LDS but whose real-part plane fits), or 0 if there is none for L.
 int row_chain_threads(int L);
+// Radix of that kernel's first stage: a thread loads elements j + t L/R of its row, t < R.
+int row_chain_first_radix(int L);
 
 // Whether the 32-bit per-lane offsets of the pass's global accesses can address its tiles.
 bool pass_offsets_fit(const PassDesc& d, int esize);

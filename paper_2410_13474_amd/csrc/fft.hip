@@ -999,9 +999,11 @@ __device__ __forceinline__ void rc_stages(float* plane, RcRegs<L, T, RAD>& v, co
 template <int... RS>
 struct Radices {};
 
-// Row 'blockIdx.x': out = st(DFT_-SGN(vec . DFT_SGN(in))), T1 and T2 the two transforms' radices
-// (T2 opens with T1's last radix).  Loads are plain copies; the store applies the axis sign and scale.
-template <int L, int T, int SGN, int... A, int... B>
+// Row 'blockIdx.x': out = st(DFT_-SGN(vec . DFT_SGN(ld(in)))) for a chain, st(DFT_SGN(ld(in)))
+// otherwise; T1 and T2 are the two transforms' radices (T2 opens with T1's last radix).  A chain
+// loads plain copies; a single transform applies everything LoadPlain describes.  The store applies
+// the axis sign and scale.
+template <int L, int T, int SGN, bool CHAIN, int... A, int... B>
 __device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, const PassDesc& d,
                                                const LoadPlain<float>& ld, const StorePlain<float>& st,
                                                const cpx<float>* __restrict__ tw, const cpx<float>* __restrict__ vec,
@@ -1015,13 +1017,45 @@ __device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, con
     const cpx<float>* rin = ld.in + row * d.in_pitch;
     cpx<float>* rout = st.out + row * d.out_pitch;
     RcRegs<L, T, R0> v;
+    const bool win = !CHAIN && ld.win_lo < ld.win_hi;
 #pragma unroll
     for (int i = 0; i < RcNb<L, T, R0>::value; ++i) {
         if (!wave_has<T>(wbase, i, LR0)) continue;
         const int j0 = tid + i * T;
         const int j = j0 < LR0 ? j0 : 0;
 #pragma unroll
-        for (int t = 0; t < R0; ++t) v[i][t] = load_at<float>(uniform_base(rin + t * LR0), (uint32_t)j * 8u);
+        for (int t = 0; t < R0; ++t) {
+            const int pos = j + t * LR0;
+            if (win) {  // outside the window the input is zero and is not read
+                v[i][t] = mk(0.0f, 0.0f);
+                if (pos >= ld.win_lo && pos < ld.win_hi)
+                    v[i][t] = load_at<float>(uniform_base(rin + t * LR0), (uint32_t)j * 8u);
+            } else {
+                v[i][t] = load_at<float>(uniform_base(rin + t * LR0), (uint32_t)j * 8u);
+            }
+        }
+        if (!CHAIN && !ld.plain) {
+#pragma unroll
+            for (int t = 0; t < R0; ++t) {
+                const int pos = j + t * LR0;
+                const bool flip = ld.sign_axis && (pos & 1);
+                const float f = flip ? -ld.scale : ld.scale;
+                v[i][t] = mk(v[i][t].x * f, (ld.conj ? -v[i][t].y : v[i][t].y) * f);
+            }
+            if (ld.mul) {
+                // the vector in factored form: element j + t LR0 is c_j a_j^t b_t, two loads per
+                // thread instead of R0 (rows would otherwise read the whole vector each)
+                const cpx<float> cj = load_at<float>(uniform_base(ld.mul), (uint32_t)(2 * j) * 8u);
+                const cpx<float> aj = load_at<float>(uniform_base(ld.mul), (uint32_t)(2 * j + 1) * 8u);
+                cpx<float> pw = cj;
+#pragma unroll
+                for (int t = 0; t < R0; ++t) {
+                    const cpx<float> bt = load_at<float>(uniform_base(ld.mul + 2 * LR0), (uint32_t)t * 8u);
+                    v[i][t] = v[i][t] * (pw * bt);
+                    if (t + 1 < R0) pw = pw * aj;
+                }
+            }
+        }
     }
     auto store = [&](auto& o) {
         constexpr int RL = sizeof(o[0]) / sizeof(o[0][0]);
@@ -1062,7 +1096,8 @@ __device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, con
         }
         rc_stages<L, T, -SGN, 1, B...>(plane, u, tw, tid, wbase, store);
     };
-    rc_stages<L, T, SGN, 1, A...>(plane, v, tw, tid, wbase, middle);
+    if constexpr (CHAIN) rc_stages<L, T, SGN, 1, A...>(plane, v, tw, tid, wbase, middle);
+    else rc_stages<L, T, SGN, 1, A...>(plane, v, tw, tid, wbase, store);
 }
 
 // Radix plans: 25600 = 32 32 25 (then 25 32 32) over 1024 threads, one butterfly per thread and
@@ -1083,21 +1118,21 @@ struct RowChainPlan<6400> {
     using B = Radices<25, 8, 32>;
 };
 
-template <int L, int SGN>
+template <int L, int SGN, bool CHAIN>
 __global__ void __launch_bounds__(RowChainPlan<L>::T)
     row_chain_kernel(PassDesc d, LoadPlain<float> ld, StorePlain<float> st, const cpx<float>* __restrict__ tw,
                      const cpx<float>* __restrict__ vec) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* plane = reinterpret_cast<float*>(smem_raw);
     using P = RowChainPlan<L>;
-    row_chain_body<L, P::T, SGN>(typename P::A{}, typename P::B{}, d, ld, st, tw, vec, plane);
+    row_chain_body<L, P::T, SGN, CHAIN>(typename P::A{}, typename P::B{}, d, ld, st, tw, vec, plane);
 }
 
-template <int L, int SGN>
+template <int L, int SGN, bool CHAIN>
 static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& ld, const StorePlain<float>& st,
                                      const cpx<float>* tw, const cpx<float>* vec, hipStream_t s) {
     static bool attr_set = false;
-    auto kern = &row_chain_kernel<L, SGN>;
+    auto kern = &row_chain_kernel<L, SGN, CHAIN>;
     const size_t shm = (size_t)rc_plane_words(L) * sizeof(float);
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -1107,6 +1142,15 @@ static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& 
     }
     hipLaunchKernelGGL(kern, dim3(d.rows), dim3(RowChainPlan<L>::T), shm, s, d, ld, st, tw, vec);
     return hipGetLastError();
+}
+
+template <int A, int... REST>
+constexpr int first_of(Radices<A, REST...>) { return A; }
+
+int row_chain_first_radix(int L) {
+    if (L == 25600) return first_of(RowChainPlan<25600>::A{});
+    if (L == 6400) return first_of(RowChainPlan<6400>::A{});
+    return 0;
 }
 
 int row_chain_threads(int L) {
@@ -1121,16 +1165,21 @@ static hipError_t launch_row_chain(const PassDesc& d, const LoadPlain<R>& ld, co
     if constexpr (sizeof(R) != 4) {
         return hipErrorInvalidValue;
     } else {
-        // plain loads only (no conjugation, sign, scale, multiply or window) and a chain vector
-        if (!ld.plain || ld.mul || ld.win_lo < ld.win_hi || !vec || d.W != 1 || d.L != d.cols ||
+        // a chain loads plain copies and multiplies by its vector between the transforms
+        if ((d.chain && (!vec || !ld.plain || ld.win_lo < ld.win_hi)) || d.W != 1 || d.L != d.cols ||
             d.nthreads != row_chain_threads(d.L))
             return hipErrorInvalidValue;
-        if (d.L == 25600)
-            return d.sign < 0 ? launch_row_chain_l<25600, -1>(d, ld, st, tw, vec, s)
-                              : launch_row_chain_l<25600, 1>(d, ld, st, tw, vec, s);
-        if (d.L == 6400)
-            return d.sign < 0 ? launch_row_chain_l<6400, -1>(d, ld, st, tw, vec, s)
-                              : launch_row_chain_l<6400, 1>(d, ld, st, tw, vec, s);
+#define NUFDS_ROWC(LL)                                                                                      \
+    if (d.L == LL) {                                                                                        \
+        if (d.chain)                                                                                        \
+            return d.sign < 0 ? launch_row_chain_l<LL, -1, true>(d, ld, st, tw, vec, s)                     \
+                              : launch_row_chain_l<LL, 1, true>(d, ld, st, tw, vec, s);                     \
+        return d.sign < 0 ? launch_row_chain_l<LL, -1, false>(d, ld, st, tw, vec, s)                        \
+                          : launch_row_chain_l<LL, 1, false>(d, ld, st, tw, vec, s);                        \
+    }
+        NUFDS_ROWC(25600)
+        NUFDS_ROWC(6400)
+#undef NUFDS_ROWC
         return hipErrorInvalidValue;
     }
 }

@@ -57,6 +57,8 @@ double stretch_extent(double s);
 void table_extent(double wavelength, double pitch, int nx, int ny, int* kxt, int* kyt);
 void chirp_vector(int M, int N, double pitch, double wavelength, double z, std::vector<double>& re,
                   std::vector<double>& im);
+void chirp_row_factors(int M, int N, double pitch, double wavelength, double z, int R, std::vector<double>& re,
+                       std::vector<double>& im);
 int tile_override();
 int col_w_override();
 
@@ -70,6 +72,7 @@ struct nufds_plan {
     int device = 0;
     size_t esize = 8;
     nufds::DevBuf spec, work1, work2, table, chirp_x, chirp_y, ax, by;
+    nufds::DevBuf chirp_xf;  // chirp_x factored for one-pass row transforms (complex64, K_ROWC rows)
     int kxt = -1, kyt = -1;
     std::shared_ptr<nufds::TwiddleCache> twiddles;
     hipEvent_t done = nullptr;

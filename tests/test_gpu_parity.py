@@ -369,6 +369,31 @@ def test_row_chain_pass_parity(prec):
     _check(H, dp, z, prec, view=view, frt_size=(6400, 720), tile_cap=4096)
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_row_transform_pass_spectrum_parity(prec):
+    """Hologram rows of 6400 under a 4096-element tile: complex64 runs each row's DFT in one pass (the
+    single-transform form of the one-pass row kernel, whose loads conjugate, centre by (-1)^n and,
+    for the oversampled spectrum, read a window of the zero-padded row); complex128 takes the
+    four-step passes.  The spectrum against the oracle's centred DFT of the (padded) hologram."""
+    say(f"row transform {prec}")
+    tol = 1e-13 if prec == "c128" else 1e-6
+    for nx, ny, over in ((6400, 40, None), (3200, 40, 2)):
+        dp, pc, H = _hologram(95 + nx // 1000, 3, nx, ny, 90.0, 2 * nx * dp_(90.0), 3 * nx * dp_(90.0))
+        _, plan = _gpu_run(H, dp, float(pc.z[0]), prec, tile_cap=4096, oversample=over)
+        got = plan.debug_copy(1).cpu().numpy().astype(np.complex128)
+        src = np.conj(_oracle_input(H, prec))
+        if over:
+            padded = np.zeros((over * ny, over * nx), dtype=np.complex128)
+            oy, ox = (over * ny - ny) // 2, (over * nx - nx) // 2
+            padded[oy:oy + ny, ox:ox + nx] = src
+            src = padded
+        ref = O.centred_dft2(src)
+        err = O.rel_l2(got, ref)
+        say(f"   {nx} x {ny} oversample {over}: rel_l2 = {err:.3e}")
+        assert got.shape == ref.shape and err <= tol
+        plan.close()
+
+
 def test_execute_is_deterministic_and_repeatable():
     say("determinism")
     n = 256

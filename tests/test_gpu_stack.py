@@ -4,6 +4,7 @@ Every depth of a stack is compared with the float64 oracle's focal stack (each d
 with the FrT size shared by the stack) and with a plan at the same depth whose FrT size is forced to
 the shared one (the same method through the chained operator passes).
 """
+import os
 import sys
 
 import numpy as np
@@ -71,6 +72,31 @@ def test_stack_matches_oracle(prec):
     sizes = {(i["mx"], i["my"]) for i in st.infos}
     b = O.plan_band(n, n, LAM, dp, 1.0e-3)
     assert sizes == {(b.mx, b.my)}
+    st.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_stack_one_pass_row_transforms_match_oracle(prec):
+    """A 3888 x 32 hologram at 120 deg whose shared FrT rows are 6400 long, under a 4096-element tile:
+    complex64 runs the stack's x transforms in one pass each, the per-depth one multiplying its chirp
+    on load from the factored form (c_j a_j^t b_t); complex128 takes the four-step passes."""
+    say(f"stack one-pass rows {prec}")
+    nx, ny = 3888, 32
+    dp, H, Ht = _holo(603, nx, ny, 120.0, prec, n_points=6)
+    zs = [2.5e-3, 3.1e-3]
+    os.environ["NUFDS_MAX_TILE_ELEMS"] = "4096"
+    try:
+        st = N.Stack(LAM, dp, nx, ny, zs, precision=prec)
+    finally:
+        os.environ.pop("NUFDS_MAX_TILE_ELEMS", None)
+    assert {i["mx"] for i in st.infos} == {6400}
+    outs = st(Ht)
+    torch.cuda.synchronize()
+    refs = O.focal_stack(H, LAM, dp, zs)
+    for z, o, r in zip(zs, outs, refs):
+        err = O.rel_l2(o.cpu().numpy().astype(np.complex128), r)
+        say(f"  z {z:.2e}: rel L2 {err:.3e}")
+        assert err <= TOL[prec]
     st.close()
 
 
