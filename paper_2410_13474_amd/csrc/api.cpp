@@ -377,11 +377,16 @@ static bool finish_desc(PassDesc& d, const Limits& lim) {
     d.logW = ilog2(d.W);
     if ((1 << d.logW) != d.W) return false;
     if ((int64_t)d.L * d.W > lim.tile_elems) return false;  // padded LDS footprint within 160 KB
-    if (!factor_radices(d.L, &d.nst, d.rad, 16)) return false;
-    // prefer one butterfly per thread and stage; else several (long single-pass rows)
-    d.nthreads = pick_threads_one(d.L, d.W, d.nst, d.rad, lim.esize == 8 ? 1024 : 512);
-    d.one_bfly = d.nthreads > 0 ? 1 : 0;
-    if (!d.one_bfly) d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
+    // radices up to 16; if no thread count fits them (a radix-2 stage with too many butterflies for
+    // one per thread, and radices beyond the register budget of several), radices up to 8
+    for (int max_radix : {16, 8}) {
+        if (!factor_radices(d.L, &d.nst, d.rad, max_radix)) return false;
+        // prefer one butterfly per thread and stage; else several (long single-pass rows)
+        d.nthreads = pick_threads_one(d.L, d.W, d.nst, d.rad, lim.esize == 8 ? 1024 : 512);
+        d.one_bfly = d.nthreads > 0 ? 1 : 0;
+        if (!d.one_bfly) d.nthreads = pick_threads(d.L, d.W, d.nst, d.rad, lim.max_elems);
+        if (d.nthreads > 0) break;
+    }
     if (d.nthreads <= 0) return false;
     return pass_offsets_fit(d, (int)lim.esize);
 }

@@ -1101,8 +1101,9 @@ __device__ __forceinline__ void row_chain_body(Radices<A...>, Radices<B...>, con
 }
 
 // Radix plans: 25600 = 32 32 25 (then 25 32 32) over 1024 threads, one butterfly per thread and
-// stage; 6400 = 32 8 25 over 256 threads, the same radices and both forms of exchange at a length
-// the tests reach with a lowered tile capacity.
+// stage; 32768 = 32 32 32 over 1024 threads (the rows of a 16384-wide hologram's oversampled
+// spectrum; its plane with pads is 144 KB); 6400 = 32 8 25 over 256 threads, the same radices and
+// both forms of exchange at a length the tests reach with a lowered tile capacity.
 template <int L>
 struct RowChainPlan;
 template <>
@@ -1110,6 +1111,12 @@ struct RowChainPlan<25600> {
     static constexpr int T = 1024;
     using A = Radices<32, 32, 25>;
     using B = Radices<25, 32, 32>;
+};
+template <>
+struct RowChainPlan<32768> {
+    static constexpr int T = 1024;
+    using A = Radices<32, 32, 32>;
+    using B = Radices<32, 32, 32>;
 };
 template <>
 struct RowChainPlan<6400> {
@@ -1149,12 +1156,14 @@ constexpr int first_of(Radices<A, REST...>) { return A; }
 
 int row_chain_first_radix(int L) {
     if (L == 25600) return first_of(RowChainPlan<25600>::A{});
+    if (L == 32768) return first_of(RowChainPlan<32768>::A{});
     if (L == 6400) return first_of(RowChainPlan<6400>::A{});
     return 0;
 }
 
 int row_chain_threads(int L) {
     if (L == 25600) return RowChainPlan<25600>::T;
+    if (L == 32768) return RowChainPlan<32768>::T;
     if (L == 6400) return RowChainPlan<6400>::T;
     return 0;
 }
@@ -1178,6 +1187,7 @@ static hipError_t launch_row_chain(const PassDesc& d, const LoadPlain<R>& ld, co
                           : launch_row_chain_l<LL, 1, false>(d, ld, st, tw, vec, s);                        \
     }
         NUFDS_ROWC(25600)
+        NUFDS_ROWC(32768)
         NUFDS_ROWC(6400)
 #undef NUFDS_ROWC
         return hipErrorInvalidValue;

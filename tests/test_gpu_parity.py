@@ -371,15 +371,17 @@ def test_row_chain_pass_parity(prec):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_row_transform_pass_spectrum_parity(prec):
-    """Hologram rows of 6400 under a 4096-element tile: complex64 runs each row's DFT in one pass (the
-    single-transform form of the one-pass row kernel, whose loads conjugate, centre by (-1)^n and,
-    for the oversampled spectrum, read a window of the zero-padded row); complex128 takes the
-    four-step passes.  The spectrum against the oracle's centred DFT of the (padded) hologram."""
+    """Hologram rows of 6400 under a 4096-element tile, and the 32768-point rows of a 16384-wide
+    hologram's oversampled spectrum: complex64 runs each row's DFT in one pass (the single-transform
+    form of the one-pass row kernel, whose loads conjugate, centre by (-1)^n and, for the oversampled
+    spectrum, read a window of the zero-padded row); complex128 takes the four-step passes.  The
+    spectrum against the oracle's centred DFT of the (padded) hologram."""
     say(f"row transform {prec}")
     tol = 1e-13 if prec == "c128" else 1e-6
-    for nx, ny, over in ((6400, 40, None), (3200, 40, 2)):
+    # the 32768-point rows exceed the default tile (its FrT rows of 25000 need it for their split)
+    for nx, ny, over, cap in ((6400, 40, None, 4096), (3200, 40, 2, 4096), (16384, 8, 2, None)):
         dp, pc, H = _hologram(95 + nx // 1000, 3, nx, ny, 90.0, 2 * nx * dp_(90.0), 3 * nx * dp_(90.0))
-        _, plan = _gpu_run(H, dp, float(pc.z[0]), prec, tile_cap=4096, oversample=over)
+        _, plan = _gpu_run(H, dp, float(pc.z[0]), prec, tile_cap=cap, oversample=over)
         got = plan.debug_copy(1).cpu().numpy().astype(np.complex128)
         src = np.conj(_oracle_input(H, prec))
         if over:
