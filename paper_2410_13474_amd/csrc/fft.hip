@@ -1138,6 +1138,7 @@ __global__ void __launch_bounds__(RowChainPlan<L>::T)
 template <int L, int SGN, bool CHAIN>
 static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& ld, const StorePlain<float>& st,
                                      const cpx<float>* tw, const cpx<float>* vec, hipStream_t s) {
+    if (d.rows <= 0) return hipSuccess;  // nothing to transform (a zero-sized grid is not a launch)
     static bool attr_set = false;
     auto kern = &row_chain_kernel<L, SGN, CHAIN>;
     const size_t shm = (size_t)rc_plane_words(L) * sizeof(float);
