@@ -23,6 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU instructions the chip can issue per second: 256 CUs, each one per clock (four SIMDs of
+# 16 lanes, a wave64 instruction taking four clocks on one), at 2.4 GHz; packed FP32 is not used
+VALU_ISSUE_PEAK = 256 * 2.4e9
 LAM = 0.5e-6
 
 WORKLOADS = {
@@ -63,6 +66,18 @@ def measured_traffic(role):
     return r["fetch_bytes"] + r["write_bytes"]
 
 
+def measured_valu(role):
+    """VALU wave-instructions per launch of a kernel role (SQ_INSTS_VALU) from the committed counter
+    summary, or None when missing or taken on different sources."""
+    try:
+        rec = json.load(open(PROFILE_JSON))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash() or role not in rec.get("roles", {}):
+        return None
+    return rec["roles"][role].get("valu_insts")
+
+
 def summarize_profile(d):
     """rocprofv3 CSVs -> profiles/counters_uwa120_16k.json and the markdown summary."""
     import csv
@@ -96,9 +111,22 @@ def summarize_profile(d):
         for i, r in enumerate(ours):
             per.setdefault(roles[i % len(roles)], []).append(float(r["Counter_Value"]) * 1024 * factor)
         counters[cname] = {k: sum(v) / len(v) for k, v in per.items()}
+    # VALU wave-instructions and waves per launch (no calibration: instruction counts)
+    valu = {}
+    for cname in ("SQ_INSTS_VALU", "SQ_WAVES"):
+        rs = [r for r in rows("valu", "counter_collection.csv") if r["Counter_Name"] == cname]
+        rs.sort(key=lambda r: int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))))
+        ours = [r for r in rs if any(k in r["Kernel_Name"] for k in OUR_KERNELS)]
+        n_steps = len(ours) // len(roles)
+        ours = ours[len(ours) - n_steps * len(roles):]
+        per = {}
+        for i, r in enumerate(ours):
+            per.setdefault(roles[i % len(roles)], []).append(float(r["Counter_Value"]))
+        valu[cname] = {k: sum(v) / len(v) for k, v in per.items()}
     for role in roles:
         out["roles"][role] = {"fetch_bytes": counters["FETCH_SIZE"].get(role),
-                              "write_bytes": counters["WRITE_SIZE"].get(role)}
+                              "write_bytes": counters["WRITE_SIZE"].get(role),
+                              "valu_insts": valu["SQ_INSTS_VALU"].get(role), "waves": valu["SQ_WAVES"].get(role)}
     stats = rows("trace", "kernel_stats.csv")
     out["kernel_stats"] = [{"kernel": short(r["Name"]), "calls": int(r["Calls"]),
                             "avg_ms": float(r["AverageNs"]) / 1e6} for r in stats]
@@ -118,6 +146,8 @@ def summarize_profile(d):
              "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --no-paper-model --copy-calibration",
              "rocprofv3 --pmc WRITE_SIZE -d $P/write -o run --output-format csv -- python3 $R/bench.py "
              "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --no-paper-model --copy-calibration",
+             "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES -d $P/valu -o run --output-format csv -- python3 $R/bench.py "
+             "--steps 2 --warmup 0 --no-cpu --no-fp64 --no-serving --no-stack --no-oversample --no-paper-model",
              "python3 $R/bench.py --summarize-profile $P", "```", "",
              "## Kernel statistics (rocprofv3 --stats, complex64 and complex128 steps and plan builds)", "",
              "| kernel | calls | average ms |", "|---|---|---|"]
@@ -125,18 +155,24 @@ def summarize_profile(d):
         if any(x in k["kernel"] for x in OUR_KERNELS + ("map_table", "tile_bounds", "synth")):
             lines.append(f"| `{k['kernel']}` | {k['calls']} | {k['avg_ms']:.3f} |")
     cal = out["calibration"]
-    lines += ["", "## HBM bytes per launch (complex64 step)", "",
+    lines += ["", "## HBM bytes and VALU instructions per launch (complex64 step)", "",
               f"Calibration: a 1 GiB device copy reads FETCH_SIZE = {cal['FETCH_SIZE']['copy_kib']:.0f} KiB "
               f"and WRITE_SIZE = {cal['WRITE_SIZE']['copy_kib']:.0f} KiB, so the counters are scaled by "
               f"{cal['FETCH_SIZE']['factor']:.4f} (fetch) and {cal['WRITE_SIZE']['factor']:.4f} (write).", "",
-              "| role | bench avg ms (HIP events) | algorithmic GB | HBM read GB | HBM written GB | traffic / algorithmic |",
-              "|---|---|---|---|---|---|"]
+              "VALU issue: SQ_INSTS_VALU (wave64 instructions) over the launch's duration, against 256 CUs "
+              "issuing one per clock at 2.4 GHz (614.4 G/s; packed FP32 is not used).", "",
+              "| role | bench avg ms (HIP events) | algorithmic GB | HBM read GB | HBM written GB | traffic / algorithmic "
+              "| VALU G instr. | VALU per wave | VALU issue / peak |",
+              "|---|---|---|---|---|---|---|---|---|"]
     for role, r in out["roles"].items():
         alg = (meta.get("bytes") or {}).get(role)
         ms_r = (meta.get("avg_ms") or {}).get(role)
         tot = (r["fetch_bytes"] or 0) + (r["write_bytes"] or 0)
+        vi, wv = r.get("valu_insts"), r.get("waves")
+        vcols = (f" {vi / 1e9:.2f} | {vi / wv:.0f} | {vi / (ms_r * 1e-3) / VALU_ISSUE_PEAK:.2f} |"
+                 if vi and wv else " - | - | - |")
         lines.append(f"| {role} | {ms_r:.3f} | {alg / 1e9:.2f} | {r['fetch_bytes'] / 1e9:.2f} | "
-                     f"{r['write_bytes'] / 1e9:.2f} | {tot / alg:.2f} |")
+                     f"{r['write_bytes'] / 1e9:.2f} | {tot / alg:.2f} |" + vcols)
     open(PROFILE_MD, "w").write("\n".join(lines) + "\n")
     return out
 
@@ -485,6 +521,11 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "bytes_per_launch": d["bytes"], "avg_ms": d["avg_ms"]}
+    # the same kernel's vector-instruction issue (counter summary of the same sources), or null
+    vi = measured_valu(dom)
+    roofline["valu_issue"] = None if not vi else {
+        "insts_per_launch": vi, "achieved_per_s": vi / (d["avg_ms"] * 1e-3), "peak_per_s": VALU_ISSUE_PEAK,
+        "frac": vi / (d["avg_ms"] * 1e-3) / VALU_ISSUE_PEAK}
 
     over = None
     if not args.no_oversample:
