@@ -378,12 +378,15 @@ def test_row_transform_pass_spectrum_parity(prec):
     spectrum against the oracle's centred DFT of the (padded) hologram."""
     say(f"row transform {prec}")
     tol = 1e-13 if prec == "c128" else 1e-6
-    # the 32768-point rows exceed the default tile (its FrT rows of 25000 need it for their split)
-    for nx, ny, over, cap in ((6400, 40, None, 4096), (3200, 40, 2, 4096), (16384, 8, 2, None)):
+    # the 32768-point rows exceed the default tile (its FrT rows of 25000 need it for their split);
+    # a converging hologram is transformed without conjugation
+    cases = ((6400, 40, None, 4096, 0), (6400, 40, None, 4096, N.FLAG_CONVERGING), (3200, 40, 2, 4096, 0),
+             (16384, 8, 2, None, 0))
+    for nx, ny, over, cap, flags in cases:
         dp, pc, H = _hologram(95 + nx // 1000, 3, nx, ny, 90.0, 2 * nx * dp_(90.0), 3 * nx * dp_(90.0))
-        _, plan = _gpu_run(H, dp, float(pc.z[0]), prec, tile_cap=cap, oversample=over)
+        _, plan = _gpu_run(H, dp, float(pc.z[0]), prec, tile_cap=cap, oversample=over, flags=flags)
         got = plan.debug_copy(1).cpu().numpy().astype(np.complex128)
-        src = np.conj(_oracle_input(H, prec))
+        src = _oracle_input(H, prec) if flags & N.FLAG_CONVERGING else np.conj(_oracle_input(H, prec))
         if over:
             padded = np.zeros((over * ny, over * nx), dtype=np.complex128)
             oy, ox = (over * ny - ny) // 2, (over * nx - nx) // 2
@@ -391,7 +394,7 @@ def test_row_transform_pass_spectrum_parity(prec):
             src = padded
         ref = O.centred_dft2(src)
         err = O.rel_l2(got, ref)
-        say(f"   {nx} x {ny} oversample {over}: rel_l2 = {err:.3e}")
+        say(f"   {nx} x {ny} oversample {over} flags {flags}: rel_l2 = {err:.3e}")
         assert got.shape == ref.shape and err <= tol
         plan.close()
 
