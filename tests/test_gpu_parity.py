@@ -367,6 +367,11 @@ def test_row_chain_pass_parity(prec):
     B = O.image_size(LAM, dp, z)
     view = dict(center_x=0.21 * B, center_y=-0.13 * B, pitch_x=0.0, pitch_y=0.0, nx=200, ny=120)
     _check(H, dp, z, prec, view=view, frt_size=(6400, 720), tile_cap=4096)
+    # FrT rows of 32768 (the radix 32 32 32 plan, past the default tile) on a 512 x 16 hologram
+    dp2, pc2, H2 = _hologram(97, 3, 512, 16, 120.0, 3 * 512 * dp, 5 * 512 * dp)
+    z2 = float(pc2.z[0])
+    my2 = N.plan_geometry(LAM, dp2, 512, 16, z2)["my"]
+    _check(H2, dp2, z2, prec, frt_size=(32768, my2))
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
