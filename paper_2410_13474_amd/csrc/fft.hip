@@ -857,8 +857,9 @@ static hipError_t launch_signed(const PassDesc& d, const LoadPlain<R>& ld, const
 
 
 // ------------------------------------------------------------ row chain in one pass
-// The chain IDFT . vec . DFT along rows whose complex64 tile exceeds LDS (25600 elements: 200 KB)
-// while a plane of their real parts fits (100 KB).  One workgroup holds one row in registers,
+// A transform, or the chain IDFT . vec . DFT, along rows whose complex64 tile exceeds LDS (25600
+// elements: 200 KB; 32768: 256 KB) while a plane of their real parts fits (100 KB; 128 KB).  One
+// workgroup holds one row in registers,
 // L / T elements per thread; every exchange between two stages passes through a float plane in
 // LDS twice, real parts and then imaginary parts.  The first transform's last stage and the
 // second's first stage have the same radix, so each lane already holds the elements
@@ -1138,6 +1139,7 @@ __global__ void __launch_bounds__(RowChainPlan<L>::T)
 template <int L, int SGN, bool CHAIN>
 static hipError_t launch_row_chain_l(const PassDesc& d, const LoadPlain<float>& ld, const StorePlain<float>& st,
                                      const cpx<float>* tw, const cpx<float>* vec, hipStream_t s) {
+    static_assert(rc_plane_words(L) * sizeof(float) <= 160 * 1024, "the plane must fit LDS");
     if (d.rows <= 0) return hipSuccess;  // nothing to transform (a zero-sized grid is not a launch)
     static bool attr_set = false;
     auto kern = &row_chain_kernel<L, SGN, CHAIN>;
