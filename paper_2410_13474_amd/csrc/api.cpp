@@ -662,7 +662,10 @@ nufds_status_t run_fft1(nufds_plan* p, const void* d_in, void* spec, void* w1, h
     const int ox = (nx - hx) / 2, oy = (ny - hy) / 2;
     const int xw_lo = sf > 1 ? ox : 0, xw_hi = sf > 1 ? ox + hx : 0;
     const int yw_lo = sf > 1 ? oy : 0, yw_hi = sf > 1 ? oy + hy : 0;
-    const cpx<R>* in = static_cast<const cpx<R>*>(d_in) - ox;    // column n of a row is hologram column n - ox
+    // column n of a row is hologram column n - ox; the base is formed as an address (the columns
+    // before the hologram lie outside the load window and are never read)
+    const cpx<R>* in =
+        reinterpret_cast<const cpx<R>*>(reinterpret_cast<uintptr_t>(d_in) - (uintptr_t)ox * sizeof(cpx<R>));
     cpx<R>* rows_out = static_cast<cpx<R>*>(spec) + (size_t)oy * nx;
     const int conj_in = (p->flags & NUFDS_FLAG_CONVERGING) ? 0 : 1;
     AxisPlan ap;
