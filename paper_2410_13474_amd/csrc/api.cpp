@@ -362,7 +362,7 @@ static Limits limits_for(size_t esize, int cap, int colw) {
     if (cap > 0) l.tile_elems = std::min(l.tile_elems, cap);
     l.row_w = esize == 8 ? 16 : 8;
     l.col_w = colw > 0 ? colw : (esize == 8 ? 32 : 16);
-    l.chain_w = esize == 8 ? 16 : 8;
+    l.chain_w = esize == 8 ? 32 : 8;
     l.max_elems = esize == 8 ? 16 : 8;
     return l;
 }
