@@ -374,6 +374,17 @@ def test_row_chain_pass_parity(prec):
     _check(H2, dp2, z2, prec, frt_size=(32768, my2))
 
 
+@pytest.mark.parametrize("flags", [N.FLAG_NO_STRETCH, N.FLAG_NO_REMAP, N.FLAG_CONVERGING,
+                                   N.FLAG_NO_STRETCH | N.FLAG_NO_REMAP])
+def test_row_chain_pass_flag_parity(flags):
+    """The one-pass x chain (complex64, FrT rows of 6400 under a 4096-element tile) under each flag."""
+    say(f"row chain flags {flags}")
+    n = 384
+    dp = dp_(120.0)
+    dp, pc, H = _hologram(94, 4, n, n, 120.0, 3 * n * dp, 5 * n * dp)
+    _check(H, dp, float(pc.z[0]), "c64", flags=flags, frt_size=(6400, 864), tile_cap=4096)
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_row_transform_pass_spectrum_parity(prec):
     """Hologram rows of 6400 under a 4096-element tile, and the 32768-point rows of a 16384-wide
